@@ -1,0 +1,140 @@
+"""CPU oracle for the per-point implicit-Euler GSM evaluation.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
+baseline may import this package; the product library never does. The
+arithmetic lives in ``automat_oracle.c`` (plain C, FP64, OpenMP, no automatic
+differentiation, dense Gaussian elimination with partial pivoting); this file
+only builds it and marshals numpy arrays.
+
+Layout: fields are numpy ``(6, n)`` float64 (component-major), phase ids
+``(n,)`` uint8, parameter rows ``(n_phases, 8)``: kind, E, nu, H, sigma_y,
+sigma0, eps0, n. Parameter gradients come back as ``(n_phases, 7)`` over
+E, nu, H, sigma_y, sigma0, eps0, n.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "automat_oracle.c")
+_SO = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+SIGMA_CRITERION = 1
+GRAD_KEYS = ("E", "nu", "H", "sigma_y", "sigma0", "eps0", "n")
+
+
+def build() -> str:
+    """Compile the oracle with gcc: -O2, no fast-math, OpenMP."""
+    tmp = _SO + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+           "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _SO)
+    return _SO
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_SO)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.oracle_evaluate.restype = ctypes.c_int
+        L.oracle_evaluate.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_void_p, ctypes.c_int, dp,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                      ctypes.c_uint, dp, dp, dp, ctypes.c_void_p]
+        L.oracle_backward.restype = ctypes.c_int
+        L.oracle_backward.argtypes = [ctypes.c_int64, dp, dp, dp, ctypes.c_void_p, ctypes.c_int,
+                                      dp, ctypes.c_double, dp, dp, dp, dp, dp]
+        L.oracle_force_potential.restype = ctypes.c_int
+        L.oracle_force_potential.argtypes = [dp, dp, dp, dp, dp]
+        L.oracle_num_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None and a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+def num_threads() -> int:
+    return int(lib().oracle_num_threads())
+
+
+def params_rows(phases) -> np.ndarray:
+    """Accepts a list of phase dicts or an (n_phases, 8) array."""
+    if isinstance(phases, np.ndarray):
+        return _f64(phases)
+    from paper_2006_04391_amd.inputs import phases_array
+    return _f64(phases_array(phases))
+
+
+def evaluate(eps, a_old, phase, phases, h=0.1, tol=1e-12, max_iter=50, tangent=False,
+             flags=0):
+    """Returns dict(sigma, a_out, tangent (36, n) or None, iters (n,) int32)."""
+    eps = _f64(eps)
+    n = eps.shape[1]
+    a_old = _f64(a_old, (6, n))
+    phase = np.ascontiguousarray(phase, dtype=np.uint8)
+    par = params_rows(phases)
+    sigma = np.empty((6, n))
+    a_out = np.empty((6, n))
+    tan = np.empty((36, n)) if tangent else None
+    iters = np.empty(n, dtype=np.int32)
+    rc = lib().oracle_evaluate(n, _dp(eps), _dp(a_old), phase.ctypes.data, par.shape[0],
+                               _dp(par), h, tol, max_iter, flags, _dp(sigma), _dp(a_out),
+                               _dp(tan), iters.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle_evaluate: invalid arguments")
+    return dict(sigma=sigma, a_out=a_out, tangent=tan, iters=iters)
+
+
+def backward(eps, a_old, a_new, phase, phases, h, grad_sigma=None, grad_a=None):
+    """Vector-Jacobian product of (sigma, a_{n+1}) at a converged step.
+
+    Returns dict(grad_eps (6, n), grad_a_old (6, n), grad_params (n_phases, 7))."""
+    eps = _f64(eps)
+    n = eps.shape[1]
+    a_old = _f64(a_old, (6, n))
+    a_new = _f64(a_new, (6, n))
+    phase = np.ascontiguousarray(phase, dtype=np.uint8)
+    par = params_rows(phases)
+    gs = None if grad_sigma is None else _f64(grad_sigma, (6, n))
+    ga = None if grad_a is None else _f64(grad_a, (6, n))
+    geps = np.empty((6, n))
+    gan = np.empty((6, n))
+    gpar = np.zeros((par.shape[0], 7))
+    rc = lib().oracle_backward(n, _dp(eps), _dp(a_old), _dp(a_new), phase.ctypes.data,
+                               par.shape[0], _dp(par), h, _dp(gs), _dp(ga), _dp(geps),
+                               _dp(gan), _dp(gpar))
+    if rc != 0:
+        raise ValueError("oracle_backward: invalid arguments")
+    return dict(grad_eps=geps, grad_a_old=gan, grad_params=gpar)
+
+
+def force_potential(phase_row, A):
+    """(Psi, f (6,), Psi'' (6, 6)) at one generalized stress."""
+    row = _f64(phase_row, (8,))
+    A = _f64(A, (6,))
+    f = np.empty(6)
+    P2 = np.empty(36)
+    psi = ctypes.c_double()
+    rc = lib().oracle_force_potential(_dp(row), _dp(A), _dp(f), _dp(P2), ctypes.byref(psi))
+    if rc != 0:
+        raise ValueError("invalid phase row")
+    return psi.value, f, P2.reshape(6, 6)
