@@ -154,6 +154,19 @@ static double proj_P(int i, int j)
     return 0.0;
 }
 
+/* g = grad J2 = (s1, s2, s3, 2 A4, 2 A5, 2 A6) with the deviator written as
+ * s1 = (2 A1 - A2 - A3) / 3 etc., which is exactly zero for a hydrostatic
+ * state (A1 = A2 = A3), so such a state has no flow at all. */
+static void deviator(const double A[6], double g[6])
+{
+    g[0] = (2.0 * A[0] - A[1] - A[2]) / 3.0;
+    g[1] = (2.0 * A[1] - A[0] - A[2]) / 3.0;
+    g[2] = (2.0 * A[2] - A[0] - A[1]) / 3.0;
+    g[3] = 2.0 * A[3];
+    g[4] = 2.0 * A[4];
+    g[5] = 2.0 * A[5];
+}
+
 /* Force potential value, gradient f = dPsi/dA and (optionally) Hessian.
  * Hand-derived:
  *   s = dev(A) (normal part), J2 = 1/2 (s1^2 + s2^2 + s3^2) + A4^2 + A5^2 + A6^2,
@@ -165,8 +178,8 @@ static double proj_P(int i, int j)
 static double force_potential(const phase_t *p, const double A[6], double f[6],
                               double P2[6][6])
 {
-    double m = (A[0] + A[1] + A[2]) / 3.0;
-    double g[6] = {A[0] - m, A[1] - m, A[2] - m, 2.0 * A[3], 2.0 * A[4], 2.0 * A[5]};
+    double g[6];
+    deviator(A, g);
     double J2 = 0.5 * (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) + A[3] * A[3] + A[4] * A[4] +
                 A[5] * A[5];
     if (p->n == 1.0 && p->sy == 0.0) {
@@ -528,8 +541,8 @@ static void backward_point(const phase_t *p, const double eps[6], const double a
     gp[2] = h * wP2AH;
     gp[3] = gp[4] = gp[5] = gp[6] = 0.0;
     if (p->kind == 1 && !(p->n == 1.0 && p->sy == 0.0)) {
-        double m = (A[0] + A[1] + A[2]) / 3.0;
-        double g[6] = {A[0] - m, A[1] - m, A[2] - m, 2.0 * A[3], 2.0 * A[4], 2.0 * A[5]};
+        double g[6];
+        deviator(A, g);
         double J2 = 0.5 * (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) + A[3] * A[3] +
                     A[4] * A[4] + A[5] * A[5];
         double q = sqrt(3.0 * J2);
@@ -548,8 +561,8 @@ static void backward_point(const phase_t *p, const double eps[6], const double a
     } else if (p->kind == 1) {
         /* n = 1, sigma_y = 0: f = 3 eps0 / (2 sigma0) g; the n-derivative of
          * r^n at n = 1 is r log r, taken from the general branch when x > 0 */
-        double m = (A[0] + A[1] + A[2]) / 3.0;
-        double g[6] = {A[0] - m, A[1] - m, A[2] - m, 2.0 * A[3], 2.0 * A[4], 2.0 * A[5]};
+        double g[6];
+        deviator(A, g);
         double J2 = 0.5 * (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) + A[3] * A[3] +
                     A[4] * A[4] + A[5] * A[5];
         double q = sqrt(3.0 * J2);
