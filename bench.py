@@ -1,0 +1,187 @@
+"""Benchmark: FP64 material-point updates/s of one implicit-Euler GSM
+evaluation batch on the 256^3 fibre microstructure (one MI355X).
+
+A step is one call of the whole per-point path (load eps, a_n, phase; AD
+residual; Newton with AD Hessian and Cholesky; stress and a_{n+1} stores)
+over all 256^3 points, inputs resident in HBM. Timed with events on the
+stream the kernels run on. Prints one JSON line.
+
+Roofline: the path streams 193 B per point (reads eps, a_n: 96 B, phase:
+1 B; writes sigma, a_{n+1}: 96 B) against 8 TB/s HBM; the dominant kernel's
+achieved algorithmic bandwidth is reported as the roofline fraction.
+The CPU baseline is the oracle (plain C, OpenMP) timed on a bounded prefix
+of the same batch.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FP64 material-point updates/s at 256^3 (% roofline); served p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+BYTES_PER_POINT = 6 * 8 + 6 * 8 + 1 + 6 * 8 + 6 * 8          # 193
+BYTES_PER_POINT_TANGENT = BYTES_PER_POINT + 36 * 8            # 481
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_calls(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    per = []
+    t0 = time.perf_counter()
+    start.record(stream)
+    for _ in range(steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        per.append((e0, e1))
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = start.elapsed_time(end)
+    each = [a.elapsed_time(b) for a, b in per]
+    return total_ms, each, wall
+
+
+def cpu_baseline(ps, budget_s=15.0):
+    """Time the oracle on growing prefixes of the batch until one takes at
+    least budget_s/3 seconds (or the whole batch is done)."""
+    import oracle
+    n_total = ps.n
+    m = 1 << 16
+    while True:
+        m = min(m, n_total)
+        eps = np.ascontiguousarray(ps.eps[:, :m])
+        a_old = np.ascontiguousarray(ps.a_old[:, :m])
+        phase = np.ascontiguousarray(ps.phase[:m])
+        t0 = time.perf_counter()
+        oracle.evaluate(eps, a_old, phase, ps.phases, h=ps.h, tol=ps.tol, max_iter=ps.max_iter)
+        dt = time.perf_counter() - t0
+        if dt >= budget_s / 3 or m == n_total:
+            return dict(value=m / dt, unit="updates/s", cores=oracle.num_threads(), kind="oracle",
+                        sample=f"first {m} of {n_total} points of the 256^3 fibre batch, "
+                               f"no tangent, {dt:.2f} s")
+        m *= 4
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--side", type=int, default=256, help="cube side (256 = the headline batch)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-tangent", action="store_true", help="skip the tangent variant")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported "
+                                   "(the per-point path shards by contiguous point ranges, "
+                                   "see the design notes)"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2006_04391_amd import api, inputs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.perf_counter()
+    ps = inputs.points_c1(N=args.side) if args.side != 256 else inputs.points_c1()
+    log(f"[bench] inputs {ps.n} points generated in {time.perf_counter() - t0:.1f} s")
+    n = ps.n
+    eps = torch.from_numpy(ps.eps).to(dev)
+    a_old = torch.from_numpy(ps.a_old).to(dev)
+    phase = torch.from_numpy(ps.phase).to(dev)
+    sigma = torch.empty_like(eps)
+    a_new = torch.empty_like(a_old)
+    stream = torch.cuda.current_stream(dev)
+
+    def step():
+        api.evaluate(eps, a_old, phase, ps.phases, ps.h, ps.tol, ps.max_iter,
+                     sigma_out=sigma, a_out=a_new)
+
+    total_ms, each, wall = time_calls(step, args.steps, args.warmup, stream)
+    ms = total_ms / args.steps
+    value = n / (ms * 1e-3)
+    avg_launch_ms = float(np.mean(each))
+    achieved = BYTES_PER_POINT * n / (avg_launch_ms * 1e-3) / 1e9
+    log(f"[bench] forward: {ms:.3f} ms/step, {value:.3e} updates/s, {achieved:.0f} GB/s")
+
+    # iteration profile of the batch (for the FLOP side of the roofline)
+    _, _, iters, cnt = api.evaluate(eps, a_old, phase, ps.phases, ps.h, ps.tol, ps.max_iter,
+                                    return_iters=True)
+    it = iters.cpu().numpy()
+    hist = {int(k): int(v) for k, v in zip(*np.unique(it, return_counts=True))}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.side}^3 periodic fibre composite (15 % fibres r=4 L=64), one "
+                        "implicit-Euler evaluation batch without tangent, h=0.1 s, tol 1e-12",
+            "points": n,
+            "newton_updates_histogram": hist,
+            "nonconverged": int(cnt.item()),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "kernel": "gsm_eval_kernel<false>",
+            "bytes_per_point": BYTES_PER_POINT,
+        },
+    }
+
+    if not args.no_tangent:
+        tan = torch.empty((36, n), dtype=torch.float64, device=dev)
+
+        def step_t():
+            api.evaluate(eps, a_old, phase, ps.phases, ps.h, ps.tol, ps.max_iter,
+                         sigma_out=sigma, a_out=a_new, tangent=True)
+        del tan
+        tt, each_t, _ = time_calls(step_t, max(3, args.steps // 4), 1, stream)
+        ms_t = tt / max(3, args.steps // 4)
+        out["tangent"] = {"ms_per_step": ms_t, "value": n / (ms_t * 1e-3), "unit": "updates/s",
+                          "hbm_gbs": BYTES_PER_POINT_TANGENT * n / (ms_t * 1e-3) / 1e9}
+        log(f"[bench] tangent: {ms_t:.3f} ms/step")
+
+    if not args.no_cpu:
+        log("[bench] timing the CPU oracle ...")
+        out["cpu_baseline"] = cpu_baseline(ps)
+        log(f"[bench] cpu baseline {out['cpu_baseline']}")
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

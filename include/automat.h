@@ -1,0 +1,167 @@
+/*
+ * automat.h -- C ABI of libautomat, an MI355X (gfx950) FP64 evaluator for
+ * generalized standard materials (GSM) by one implicit-Euler step per
+ * material point.
+ *
+ * The method (AutoMat paper):
+ *  - a GSM is given by a free energy omega(eps, a) and a force potential
+ *    Psi(A); sigma = d omega / d eps and a' = dPsi/dA (-d omega / d a)
+ *    (Section "Generalized Standard Materials", equations gsm_sigma and
+ *    gsm_internal);
+ *  - one material-law evaluation takes eps_{n+1} and a_n and returns
+ *    a_{n+1}, sigma_{n+1} and optionally the consistent tangent
+ *    C_{n+1} = d sigma_{n+1} / d eps_{n+1} (same section, the evaluation
+ *    contract). Implicit Euler evaluates the rate at t_{n+1} only, so eps_n
+ *    is not an input;
+ *  - the step a_{n+1} = a_n + h f(eps_{n+1}, a_{n+1}) is solved by Newton
+ *    with gradients and Hessians of omega and Psi from automatic
+ *    differentiation, and the tangent follows from the implicit function
+ *    theorem with the Newton matrix at the converged point (Section
+ *    "Single Implicit Euler Step", equations implicit_euler and
+ *    tangent_formula);
+ *  - the material family is the Michel-Suquet elasto-viscoplastic GSM
+ *    (Section "Example", equations michel_suquet_omega and
+ *    michel_suquet_psi): kind 1; kind 0 is its purely elastic special case
+ *    (Psi = 0).
+ *
+ * Conventions for every entry point:
+ *  - all floating point is IEEE double (FP64); units are the caller's
+ *    (the presets use MPa and s);
+ *  - strains and internal variables are 6-vectors in engineering-shear Voigt
+ *    order (11, 22, 33, 23, 13, 12); stresses are plain Voigt in the same
+ *    order;
+ *  - fields are device pointers in structure-of-arrays, component-major
+ *    layout with leading dimension n: component c of point i is at
+ *    ptr[c * n + i]. A tangent field holds 36 components, row-major 6x6 per
+ *    point: entry (r, c) of point i is at ptr[(6 * r + c) * n + i];
+ *  - phase ids are uint8 per point, indexing automat_params.phase;
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Calls are asynchronous and stream-ordered; the library keeps no pointer
+ *    after it returns;
+ *  - the caller owns all memory. Output arrays must not alias inputs, except
+ *    that a_out may equal a_old (in-place update);
+ *  - return value 0 on success, a negative AUTOMAT_E* code otherwise; an
+ *    error return launches nothing.
+ */
+#ifndef AUTOMAT_H
+#define AUTOMAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AUTOMAT_MAX_PHASES 16
+/* Differentiable material parameters, in this order:
+ * E, nu, H, sigma_y, sigma0, eps0, n. */
+#define AUTOMAT_NPAR 7
+
+#define AUTOMAT_OK 0
+#define AUTOMAT_EINVAL (-1)  /* bad pointer, size, scalar or parameter */
+#define AUTOMAT_EHIP (-2)    /* HIP runtime or launch error */
+#define AUTOMAT_ENOMEM (-3)  /* device or host allocation failed */
+#define AUTOMAT_EBUDGET (-4) /* serving request larger than the memory budget */
+
+/* Flags of automat_evaluate_ex. */
+#define AUTOMAT_SIGMA_CRITERION 1u /* stop Newton on ||C F||_inf <= tol ||sigma||_inf,
+                                      i.e. converge the stress (Section "Stress-Driven
+                                      Error Control", last paragraph) */
+
+/* One material phase (Section "Example", Table misu_parameters names the
+ * same quantities).
+ *  kind     0 = elastic (Psi = 0), 1 = Michel-Suquet elasto-viscoplastic
+ *  E, nu    Young's modulus (> 0) and Poisson's ratio (-1 < nu < 0.5)
+ *  H        linear kinematic hardening modulus (>= 0)
+ *  sigma_y  initial yield stress (>= 0)
+ *  sigma0   drag stress sigma_d (> 0)
+ *  eps0     reference strain rate (>= 0)
+ *  n        rate sensitivity (>= 1)
+ * For kind 0 only E and nu are read and checked. */
+typedef struct automat_phase {
+    int32_t kind;
+    int32_t reserved;
+    double E, nu, H, sigma_y, sigma0, eps0, n;
+} automat_phase;
+
+/* Host struct, read during the call and copied into the launch. */
+typedef struct automat_params {
+    int32_t n_phases; /* 1 .. AUTOMAT_MAX_PHASES */
+    int32_t reserved;
+    automat_phase phase[AUTOMAT_MAX_PHASES];
+} automat_params;
+
+/* One implicit-Euler material-law evaluation of n points.
+ *
+ *  eps_new     [6][n] strain at t_{n+1}                               (in)
+ *  a_old       [6][n] internal variables a_n (viscoplastic strain)    (in)
+ *  phase       [n]    phase id per point                              (in)
+ *  params      host   phase table                                     (in)
+ *  h           step length t_{n+1} - t_n, finite and > 0
+ *  tol         Newton tolerance (> 0): converged when
+ *              ||F||_inf <= tol ||a_{n+1} - a_n||_inf after >= 1 update,
+ *              or when F vanishes exactly (no flow)
+ *  max_iter    maximum number of Newton updates (>= 1)
+ *  sigma_out   [6][n] stress sigma_{n+1}                              (out)
+ *  a_out       [6][n] a_{n+1}, may equal a_old; NULL skips the write  (out)
+ *  tangent_out [36][n] consistent tangent, NULL skips it              (out)
+ *
+ * Per-point failures do not fail the call: a point that does not converge
+ * keeps its last Newton iterate; a point with non-finite input or a phase id
+ * >= n_phases gets NaN outputs. Use automat_evaluate_ex to see them.
+ * n = 0 is a no-op returning 0. Errors: AUTOMAT_EINVAL (NULL required
+ * pointer, n < 0, h or tol not finite and > 0, max_iter < 1, invalid
+ * params), AUTOMAT_EHIP. */
+int32_t automat_evaluate(int64_t n, const double *eps_new, const double *a_old,
+                         const uint8_t *phase, const automat_params *params, double h,
+                         double tol, int32_t max_iter, double *sigma_out, double *a_out,
+                         double *tangent_out, void *stream);
+
+/* As automat_evaluate, plus
+ *  iters_out    [n] device int32, number of Newton updates per point, -1 if not
+ *               converged or invalid input; NULL skips it             (out)
+ *  nonconverged device uint64 counter, incremented once per point with
+ *               iters = -1 (not reset by the call); NULL skips it     (inout)
+ *  flags        AUTOMAT_SIGMA_CRITERION or 0 */
+int32_t automat_evaluate_ex(int64_t n, const double *eps_new, const double *a_old,
+                            const uint8_t *phase, const automat_params *params, double h,
+                            double tol, int32_t max_iter, double *sigma_out, double *a_out,
+                            double *tangent_out, int32_t *iters_out, uint64_t *nonconverged,
+                            uint32_t flags, void *stream);
+
+/* Vector-Jacobian product of one evaluation at its converged state
+ * (implicit function theorem through the Newton system of Section "Single
+ * Implicit Euler Step"; the step length carries no derivative and the
+ * equation solve is treated as one elementary operation, as in Theorem
+ * ad_integration_step).
+ *
+ *  eps_new, a_old, phase, params, h   as passed to automat_evaluate  (in)
+ *  a_new       [6][n] a_{n+1} returned by the forward call            (in)
+ *  grad_sigma  [6][n] cotangent of sigma_{n+1}; NULL = zero           (in)
+ *  grad_a      [6][n] cotangent of a_{n+1}; NULL = zero               (in)
+ *  grad_eps    [6][n] cotangent of eps_{n+1}                          (out)
+ *  grad_a_old  [6][n] cotangent of a_n; NULL skips it                 (out)
+ *  grad_params [n_phases][AUTOMAT_NPAR] device array, ACCUMULATED (+=)
+ *              over points, in the order E, nu, H, sigma_y, sigma0,
+ *              eps0, n; NULL skips it                               (inout)
+ * Points with a phase id >= n_phases get NaN cotangents and add nothing.
+ * Errors as automat_evaluate. */
+int32_t automat_evaluate_backward(int64_t n, const double *eps_new, const double *a_old,
+                                  const double *a_new, const uint8_t *phase,
+                                  const automat_params *params, double h,
+                                  const double *grad_sigma, const double *grad_a,
+                                  double *grad_eps, double *grad_a_old, double *grad_params,
+                                  void *stream);
+
+/* Human-readable text of a return code. */
+const char *automat_strerror(int32_t code);
+
+/* Library version string. */
+const char *automat_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AUTOMAT_H */

@@ -1,0 +1,370 @@
+// automat.hip -- gfx950 kernels and C ABI for the per-point implicit-Euler
+// GSM evaluation (forward, forward + tangent) and its vector-Jacobian
+// product. See include/automat.h for the contract.
+//
+// Launch shape: one lane per material point, wave64, 256 lanes per block.
+// Fields are structure-of-arrays, so each of the 12 input and 12 output
+// component streams of a wave is one contiguous 512-byte segment. The grid
+// is sized to the resident capacity of the device and strides over 256-point
+// tiles; every block first builds the per-phase constant table in LDS (from
+// the AD Hessian of the free energy), then reuses it for all its tiles.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+
+#include "automat.h"
+#include "gsm_point.hpp"
+#include "host_common.hpp"
+
+namespace automat {
+
+using Model = MSGSM;
+using PC = PhaseConst<Model>;
+
+constexpr int kBlock = 256;
+
+struct EvalArgs {
+    int64_t n;
+    const double *eps;
+    const double *a_old;
+    const uint8_t *phase;
+    double *sigma;
+    double *a_out;
+    double *tangent;
+    int32_t *iters;
+    unsigned long long *nonconv;
+    double h, tol;
+    int32_t max_iter;
+    uint32_t flags;
+    int32_t n_phases;
+    int32_t reserved;
+    Model::Phase phases[AUTOMAT_MAX_PHASES];
+};
+
+__device__ __forceinline__ bool finite6(const double *x) {
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) ok = ok && isfinite(x[i]);
+    return ok;
+}
+
+// Count lanes with a non-converged or invalid point, one atomic per wave.
+__device__ __forceinline__ void count_failures(unsigned long long *counter, bool failed) {
+    const unsigned long long mask = __ballot(failed);
+    if (counter && mask) {
+        const int leader = __ffsll((long long)mask) - 1;
+        if ((int)(threadIdx.x & 63) == leader) atomicAdd(counter, (unsigned long long)__popcll(mask));
+    }
+}
+
+template <bool TANGENT>
+__global__ __launch_bounds__(kBlock) void gsm_eval_kernel(const EvalArgs args) {
+    extern __shared__ double smem_raw[];
+    PC *tab = reinterpret_cast<PC *>(smem_raw);
+    for (int k = threadIdx.x; k < args.n_phases; k += blockDim.x)
+        build_phase_const<Model>(args.phases[k], tab[k], TANGENT);
+    __syncthreads();
+
+    const int64_t n = args.n;
+    const double h = args.h;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n; base += stride) {
+        const int64_t i = base + threadIdx.x;
+        if (i >= n) continue;
+
+        double eps[6], an[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            eps[c] = __builtin_nontemporal_load(args.eps + c * n + i);
+            an[c] = __builtin_nontemporal_load(args.a_old + c * n + i);
+        }
+        const int pid = args.phase[i];
+        const bool valid = pid < args.n_phases && finite6(eps) && finite6(an);
+        const PC &pc = tab[valid ? pid : 0];
+        const Model::Phase &prm = pc.prm;
+        const bool newton = valid && Model::flows(prm);
+
+        double D[6] = {0, 0, 0, 0, 0, 0};
+        Resid cur;
+        double phi = 0.0;
+        int status = valid ? 0 : -1;
+        if (newton) {
+            residual<Model>(prm, eps, an, D, h, cur);
+            phi = h * cur.psi;
+        }
+        bool done = !newton;
+        int k = 0;
+        for (;;) {
+            if (!done) {
+                bool zero = true;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) zero = zero && (cur.F[c] == 0.0);
+                bool conv = zero;
+                if (!conv && k >= 1) {
+                    if (args.flags & AUTOMAT_SIGMA_CRITERION)
+                        conv = sigma_converged<Model>(prm, eps, an, D, cur.F, args.tol);
+                    else
+                        conv = la::norm_inf6(cur.F) <= args.tol * la::norm_inf6(D);
+                }
+                if (conv) {
+                    done = true;
+                    status = k;
+                } else if (k >= args.max_iter) {
+                    done = true;
+                    status = -1;
+                }
+            }
+            if (__ballot(!done) == 0) break;
+            if (!done) {
+                // Newton matrix M = K^-1 + h Psi'' and its Cholesky factor
+                double y[6], delta[6];
+                bool spd;
+                {
+                    double M[21], idg[6];
+                    Model::psi_hess(prm, cur.A, M);
+#pragma unroll
+                    for (int c = 0; c < 21; ++c) M[c] = pc.Kinv[c] + h * M[c];
+                    spd = la::cholesky6(M, idg);
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) y[c] = cur.F[c];
+                    la::chol_solve6(M, idg, y);
+                }
+                if (!spd) {
+                    done = true;
+                    status = -1;
+                } else {
+                    la::symv6(pc.Kinv, y, delta);
+                    const double slope = la::dot6(cur.F, y);
+                    const double s1 = la::dot6(D, y), s2 = la::dot6(delta, y);
+                    const double psi0 = cur.psi;
+                    double t = 1.0, dphi, Dt[6];
+                    for (;;) {
+#pragma unroll
+                        for (int c = 0; c < 6; ++c) Dt[c] = D[c] - t * delta[c];
+                        residual<Model>(prm, eps, an, Dt, h, cur);
+                        dphi = -t * s1 + 0.5 * t * t * s2 + h * (cur.psi - psi0);
+                        if (dphi <= -1e-4 * t * slope + 1e-13 * phi || t < 0x1p-30) break;
+                        t *= 0.5;
+                    }
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) D[c] = Dt[c];
+                    phi += dphi;
+                    ++k;
+                }
+            }
+        }
+
+        // outputs
+        double sig[6], anew[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) anew[c] = newton ? an[c] + D[c] : an[c];
+        if (valid) {
+            Model::stress(prm, eps, anew, sig);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) sig[c] = anew[c] = NAN;
+        }
+#pragma unroll
+        for (int c = 0; c < 6; ++c) __builtin_nontemporal_store(sig[c], args.sigma + c * n + i);
+        if (args.a_out) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) __builtin_nontemporal_store(anew[c], args.a_out + c * n + i);
+        }
+        if constexpr (TANGENT) {
+            double C[21];
+            if (newton) {
+                double M[21], idg[6];
+                Model::psi_hess(prm, cur.A, M);
+#pragma unroll
+                for (int c = 0; c < 21; ++c) M[c] = pc.Kinv[c] + h * M[c];
+                la::cholesky6(M, idg);
+                double W[6][6];
+#pragma unroll
+                for (int j = 0; j < 6; ++j) {
+                    double col[6];
+#pragma unroll
+                    for (int r = 0; r < 6; ++r) col[r] = pc.R[r * 6 + j];
+                    la::forward6(M, idg, col);
+#pragma unroll
+                    for (int r = 0; r < 6; ++r) W[r][j] = col[r];
+                }
+#pragma unroll
+                for (int r = 0; r < 6; ++r)
+#pragma unroll
+                    for (int c = 0; c <= r; ++c) {
+                        double s = pc.C0[la::pk(r, c)];
+#pragma unroll
+                        for (int q = 0; q < 6; ++q) s += W[q][r] * W[q][c];
+                        C[la::pk(r, c)] = s;
+                    }
+            } else if (valid) {
+#pragma unroll
+                for (int c = 0; c < 21; ++c) C[c] = pc.Cee[c];
+            } else {
+#pragma unroll
+                for (int c = 0; c < 21; ++c) C[c] = NAN;
+            }
+#pragma unroll
+            for (int r = 0; r < 6; ++r)
+#pragma unroll
+                for (int c = 0; c < 6; ++c)
+                    __builtin_nontemporal_store(C[la::pk(r, c)], args.tangent + (6 * r + c) * n + i);
+        }
+        if (args.iters) args.iters[i] = status;
+        count_failures(args.nonconv, status < 0);
+    }
+}
+
+// --------------------------------------------------------------------------
+// host side
+// --------------------------------------------------------------------------
+
+struct DeviceInfo {
+    int cus = 0;
+    int blocks_fwd = 0, blocks_tan = 0;
+};
+
+static std::mutex g_mutex;
+static DeviceInfo g_dev[64];
+static bool g_dev_init[64];
+
+static int32_t device_info(DeviceInfo &out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return AUTOMAT_EHIP;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    if (!g_dev_init[dev]) {
+        DeviceInfo d;
+        if (hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return AUTOMAT_EHIP;
+        const size_t smem = AUTOMAT_MAX_PHASES * sizeof(PC);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&d.blocks_fwd, gsm_eval_kernel<false>,
+                                                         kBlock, smem) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&d.blocks_tan, gsm_eval_kernel<true>,
+                                                         kBlock, smem) != hipSuccess)
+            return AUTOMAT_EHIP;
+        if (d.blocks_fwd < 1) d.blocks_fwd = 1;
+        if (d.blocks_tan < 1) d.blocks_tan = 1;
+        g_dev[dev] = d;
+        g_dev_init[dev] = true;
+    }
+    out = g_dev[dev];
+    return AUTOMAT_OK;
+}
+
+int32_t device_cus(int *cus) {
+    DeviceInfo d;
+    const int32_t rc = device_info(d);
+    if (rc == AUTOMAT_OK) *cus = d.cus;
+    return rc;
+}
+
+static bool valid_phase(const automat_phase &p) {
+    if (!(p.kind == 0 || p.kind == 1)) return false;
+    if (!(p.E > 0.0) || !std::isfinite(p.E)) return false;
+    if (!(p.nu > -1.0 && p.nu < 0.5)) return false;
+    if (p.kind == 1) {
+        if (!(p.H >= 0.0) || !std::isfinite(p.H)) return false;
+        if (!(p.sigma_y >= 0.0) || !std::isfinite(p.sigma_y)) return false;
+        if (!(p.sigma0 > 0.0) || !std::isfinite(p.sigma0)) return false;
+        if (!(p.eps0 >= 0.0) || !std::isfinite(p.eps0)) return false;
+        if (!(p.n >= 1.0) || !std::isfinite(p.n)) return false;
+    }
+    return true;
+}
+
+int32_t copy_params(const automat_params *params, Model::Phase *dst, int32_t *n_phases) {
+    if (!params) return AUTOMAT_EINVAL;
+    if (params->n_phases < 1 || params->n_phases > AUTOMAT_MAX_PHASES) return AUTOMAT_EINVAL;
+    for (int k = 0; k < params->n_phases; ++k) {
+        const automat_phase &p = params->phase[k];
+        if (!valid_phase(p)) return AUTOMAT_EINVAL;
+        Model::Phase q;
+        q.kind = p.kind;
+        q.reserved = 0;
+        q.E = p.E;
+        q.nu = p.nu;
+        q.H = p.kind == 1 ? p.H : 0.0;
+        q.sy = p.kind == 1 ? p.sigma_y : 0.0;
+        q.s0 = p.kind == 1 ? p.sigma0 : 1.0;
+        q.e0 = p.kind == 1 ? p.eps0 : 0.0;
+        q.n = p.kind == 1 ? p.n : 1.0;
+        dst[k] = q;
+    }
+    for (int k = params->n_phases; k < AUTOMAT_MAX_PHASES; ++k) std::memset(&dst[k], 0, sizeof dst[k]);
+    *n_phases = params->n_phases;
+    return AUTOMAT_OK;
+}
+
+}  // namespace automat
+
+using namespace automat;
+
+extern "C" int32_t automat_evaluate_ex(int64_t n, const double *eps_new, const double *a_old,
+                                       const uint8_t *phase, const automat_params *params,
+                                       double h, double tol, int32_t max_iter, double *sigma_out,
+                                       double *a_out, double *tangent_out, int32_t *iters_out,
+                                       uint64_t *nonconverged, uint32_t flags, void *stream) {
+    if (n < 0) return AUTOMAT_EINVAL;
+    if (!std::isfinite(h) || !(h > 0.0) || !std::isfinite(tol) || !(tol > 0.0) || max_iter < 1)
+        return AUTOMAT_EINVAL;
+    if (flags & ~AUTOMAT_SIGMA_CRITERION) return AUTOMAT_EINVAL;
+    EvalArgs args;
+    std::memset(&args, 0, sizeof args);
+    int32_t rc = copy_params(params, args.phases, &args.n_phases);
+    if (rc) return rc;
+    if (n == 0) return AUTOMAT_OK;
+    if (!eps_new || !a_old || !phase || !sigma_out) return AUTOMAT_EINVAL;
+    args.n = n;
+    args.eps = eps_new;
+    args.a_old = a_old;
+    args.phase = phase;
+    args.sigma = sigma_out;
+    args.a_out = a_out;
+    args.tangent = tangent_out;
+    args.iters = iters_out;
+    args.nonconv = reinterpret_cast<unsigned long long *>(nonconverged);
+    args.h = h;
+    args.tol = tol;
+    args.max_iter = max_iter;
+    args.flags = flags;
+
+    DeviceInfo dev;
+    rc = device_info(dev);
+    if (rc) return rc;
+    const int64_t tiles = (n + kBlock - 1) / kBlock;
+    const int64_t cap = (int64_t)dev.cus * (tangent_out ? dev.blocks_tan : dev.blocks_fwd);
+    const int grid = (int)(tiles < cap ? tiles : cap);
+    const size_t smem = (size_t)args.n_phases * sizeof(PC);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (tangent_out)
+        hipLaunchKernelGGL(gsm_eval_kernel<true>, dim3(grid), dim3(kBlock), smem, s, args);
+    else
+        hipLaunchKernelGGL(gsm_eval_kernel<false>, dim3(grid), dim3(kBlock), smem, s, args);
+    if (hipGetLastError() != hipSuccess) return AUTOMAT_EHIP;
+    return AUTOMAT_OK;
+}
+
+extern "C" int32_t automat_evaluate(int64_t n, const double *eps_new, const double *a_old,
+                                    const uint8_t *phase, const automat_params *params, double h,
+                                    double tol, int32_t max_iter, double *sigma_out, double *a_out,
+                                    double *tangent_out, void *stream) {
+    return automat_evaluate_ex(n, eps_new, a_old, phase, params, h, tol, max_iter, sigma_out,
+                               a_out, tangent_out, nullptr, nullptr, 0u, stream);
+}
+
+extern "C" const char *automat_strerror(int32_t code) {
+    switch (code) {
+    case AUTOMAT_OK: return "success";
+    case AUTOMAT_EINVAL: return "invalid argument";
+    case AUTOMAT_EHIP: return "HIP runtime or launch error";
+    case AUTOMAT_ENOMEM: return "out of memory";
+    case AUTOMAT_EBUDGET: return "request exceeds the memory budget";
+    default: return "unknown error";
+    }
+}
+
+extern "C" const char *automat_version(void) { return "automat-gfx950 0.1"; }
