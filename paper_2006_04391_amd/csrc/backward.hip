@@ -14,7 +14,9 @@
 //              + d/dp [h w . dPsi/dA]                        (sigma_y, sigma0, eps0, n)
 //
 // J^T = K M with the same symmetric M = K^{-1} + h Psi'' the forward solve
-// factors, so w = M^{-1} K^{-1} abar (Cholesky) and h Psi'' w = K^{-1} abar - K^{-1} w.
+// factors, so w = M^{-1} K^{-1} abar (Cholesky); h Psi'' w is one more
+// Hessian-vector pass (not K^{-1} abar - K^{-1} w, which cancels when the
+// step is nearly elastic).
 // Every second derivative is a forward-over-reverse pass of the AD layer:
 // one over omega seeded with gs on eps, one over omega seeded with (gs, -v)
 // and E, nu, H as leaves, one over Psi seeded with h w and its four
@@ -103,14 +105,11 @@ __global__ __launch_bounds__(kBlock) void gsm_backward_kernel(const BackArgs arg
 #pragma unroll
                 for (int c = 0; c < 6; ++c) w[c] = r[c];
                 la::chol_solve6(M, idg, w);
-                double kw[6];
-                la::symv6(pc.Kinv, w, kw);
+                double hw[6];
 #pragma unroll
-                for (int c = 0; c < 6; ++c) {
-                    v[c] = r[c] - kw[c];    // h Psi'' w
-                    kw[c] = h * w[c];
-                }
-                Model::psi_param_partials(prm, A, kw, gp + 3);
+                for (int c = 0; c < 6; ++c) hw[c] = h * w[c];
+                Model::psi_hvp(prm, A, hw, v);   // v = h Psi'' w
+                Model::psi_param_partials(prm, A, hw, gp + 3);
             } else {
 #pragma unroll
                 for (int c = 0; c < 6; ++c) {

@@ -155,6 +155,20 @@ struct MSGSM {
 
     // ---- second-order quantities for the vector-Jacobian product ----------
 
+    // Psi''(A) w by one forward-over-reverse pass (same form of Psi as the
+    // Newton solve).
+    AD_FN static void psi_hvp(const Phase &p, const double *A, const double *w, double *out) {
+        Leaves6<PS_A> la(A);
+        ad::VecDir<6, PS_A> dir;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) dir.d[i] = w[i];
+        ad::GradT<6, PS_A> acc;
+        with_psi(la, p.sy, p.s0, p.e0, p.n, p.sy == 0.0,
+                 [&](const auto &e) { ad::hess_vec(e, dir, acc); });
+#pragma unroll
+        for (int i = 0; i < 6; ++i) out[i] = acc.g[i];
+    }
+
     // d^2 omega/(d x d eps_j) . u for x in (eps, a): returns the eps part in
     // ge and the a part in ga, i.e. (omega_ee u, omega_ae u).
     AD_FN static void omega_hvp_eps(const Phase &p, const double *eps, const double *a,

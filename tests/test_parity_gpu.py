@@ -127,7 +127,7 @@ def test_hydrostatic_points_do_not_flow():
 def test_nonconvergence_and_invalid_points_flagged():
     from paper_2006_04391_amd import api
     ps = inputs.points_random(300, seed=27, phases=inputs.paper_phases(), e11=5e-2, std=1e-2,
-                              a_std=1e-3, incl_frac=0.0)
+                              a_std=1e-3, incl_frac=0.3)
     ps.eps[1, 5] = np.nan
     ps.phase[7] = 9                          # no such phase
     g, ref = run_both(ps, max_iter=1, h=5.0)
