@@ -1,34 +1,41 @@
 // ad.hpp -- expression-level automatic differentiation for device code.
 //
 // The AD design of the paper's Section "Automatic Differentiation on GPUs",
-// rebuilt for HIP:
+// rebuilt for HIP on gfx950:
 //  * operator overloading builds an expression-template tree whose nodes
 //    store their arguments (leaves by reference, inner nodes by value); no
 //    arithmetic happens until the tree is evaluated (Figure reverse_mode);
 //  * every node offers v() (forward evaluation) and back() (reverse
 //    propagation of an adjoint); the curiously recurring template pattern
 //    resolves the interface at compile time;
-//  * there is no tape: back() re-evaluates the argument subtrees it needs
-//    (recomputation instead of taping). Everything is inlined into one
-//    kernel, so the compiler sees the whole graph, merges the repeated
-//    subexpressions and keeps all AD state in registers;
+//  * there is no tape: back() re-evaluates the argument values and tangents
+//    it needs (recomputation instead of taping). Everything is inlined into
+//    one kernel, so the compiler sees the whole graph and keeps all AD state
+//    in registers;
 //  * the second-order extension is written out explicitly for every
 //    elementary operation (not by nesting first-order types): back() carries
-//    an adjoint bv together with its tangent bt in one direction, which
-//    gives forward-over-reverse Hessian-vector products ("adjoints of
-//    tangents");
-//  * a direction object supplies each leaf's tangent seed. Seeds that are
-//    zero by construction have the empty type Zero, and arithmetic on Zero
-//    folds away at compile time, so a unit-direction Hessian pass costs only
-//    the non-zero work and a first-order pass (all seeds Zero) costs exactly a
-//    reverse sweep;
+//    an adjoint bv together with its tangents bt, which gives
+//    forward-over-reverse Hessian-vector products ("adjoints of tangents");
+//  * the tangents are a vector (forward vector mode): one reverse sweep
+//    carries all directions at once, so a full 6x6 Hessian costs one sweep
+//    instead of six;
+//  * every component of a tangent vector has its own static type, a double
+//    or the empty type Zero, and arithmetic on Zero folds away at compile
+//    time. Unit seeds therefore cost only the structurally non-zero work, and
+//    a first-order sweep (empty tangent vector) is exactly a reverse sweep;
 //  * leaves carry a compile-time id. An accumulator picks the ids it
 //    collects; adjoints flowing into other leaves are dead code and are
 //    removed, which is how partials with respect to one argument group are
 //    taken without propagating into the other (mixed-order evaluation).
 //
-// All functions are __host__ __device__ so the layer can be exercised on
-// the CPU as well.
+// One deviation from pure recomputation: nodes whose partials need
+// transcendental functions or divisions (pow, sqrt, exp, log, division)
+// compute them once per sweep in a forward prep() pass and keep them in the
+// node. The compiler cannot merge repeated inlined exp/log sequences, so
+// recomputing them would repeat the most expensive instructions of the
+// sweep; cheap arithmetic is still recomputed.
+//
+// All functions are __host__ __device__ so the layer can run on the CPU too.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -37,6 +44,8 @@
 #include <type_traits>
 
 #define AD_FN __host__ __device__ __forceinline__
+
+#include "fastmath.hpp"
 
 namespace automat {
 namespace ad {
@@ -56,13 +65,11 @@ AD_FN Zero operator-(Zero) { return {}; }
 AD_FN Zero operator*(Zero, Zero) { return {}; }
 AD_FN Zero operator*(Zero, double) { return {}; }
 AD_FN Zero operator*(double, Zero) { return {}; }
-AD_FN Zero operator/(Zero, double) { return {}; }
 AD_FN double &operator+=(double &a, Zero) { return a; }
 
 template <class T>
 inline constexpr bool is_zero_v = std::is_same_v<std::decay_t<T>, Zero>;
 
-// c ? x : 0 for a double, Zero stays Zero
 AD_FN double keep_if(bool c, double x) { return c ? x : 0.0; }
 AD_FN Zero keep_if(bool, Zero) { return {}; }
 
@@ -70,37 +77,123 @@ AD_FN Zero keep_if(bool, Zero) { return {}; }
 AD_FN double sq(double x) { return x * x; }
 
 // --------------------------------------------------------------------------
+// tangent vectors with per-component static types
+// --------------------------------------------------------------------------
+template <class... Ts>
+struct TV;
+template <>
+struct TV<> {
+    static constexpr int size = 0;
+};
+template <class T, class... Ts>
+struct TV<T, Ts...> {
+    static constexpr int size = 1 + sizeof...(Ts);
+    T h;
+    TV<Ts...> t;
+};
+
+template <class H, class... Ts>
+AD_FN TV<H, Ts...> cons(H h, const TV<Ts...> &t) {
+    return TV<H, Ts...>{h, t};
+}
+
+AD_FN TV<> operator+(const TV<> &, const TV<> &) { return {}; }
+template <class A, class... As, class B, class... Bs>
+AD_FN auto operator+(const TV<A, As...> &a, const TV<B, Bs...> &b) {
+    return cons(a.h + b.h, a.t + b.t);
+}
+AD_FN TV<> operator-(const TV<> &, const TV<> &) { return {}; }
+template <class A, class... As, class B, class... Bs>
+AD_FN auto operator-(const TV<A, As...> &a, const TV<B, Bs...> &b) {
+    return cons(a.h - b.h, a.t - b.t);
+}
+AD_FN TV<> operator-(const TV<> &) { return {}; }
+template <class A, class... As>
+AD_FN auto operator-(const TV<A, As...> &a) {
+    return cons(-a.h, -a.t);
+}
+AD_FN TV<> operator*(double, const TV<> &) { return {}; }
+template <class A, class... As>
+AD_FN auto operator*(double s, const TV<A, As...> &a) {
+    return cons(s * a.h, s * a.t);
+}
+template <class... As>
+AD_FN auto operator*(const TV<As...> &a, double s) {
+    return s * a;
+}
+AD_FN TV<> keep_if(bool, const TV<> &) { return {}; }
+template <class A, class... As>
+AD_FN auto keep_if(bool c, const TV<A, As...> &a) {
+    return cons(keep_if(c, a.h), keep_if(c, a.t));
+}
+
+// Vector of N structural zeros.
+template <int N>
+struct zeros_t {
+    using type = decltype(cons(Zero{}, typename zeros_t<N - 1>::type{}));
+};
+template <>
+struct zeros_t<0> {
+    using type = TV<>;
+};
+template <int N>
+using Zeros = typename zeros_t<N>::type;
+
+// Component J of a tangent vector.
+template <int J, class... Ts>
+AD_FN auto get(const TV<Ts...> &v) {
+    if constexpr (J == 0)
+        return v.h;
+    else
+        return get<J - 1>(v.t);
+}
+
+// Unit vector e_K of length N (1.0 at K, Zero elsewhere).
+template <int N, int K, int J = 0>
+AD_FN auto unit_tv() {
+    if constexpr (J == N)
+        return TV<>{};
+    else if constexpr (J == K)
+        return cons(1.0, unit_tv<N, K, J + 1>());
+    else
+        return cons(Zero{}, unit_tv<N, K, J + 1>());
+}
+
+// --------------------------------------------------------------------------
 // directions (tangent seeds of the leaves)
 // --------------------------------------------------------------------------
 
-// No direction: first-order reverse sweep.
+// No direction: first-order reverse sweep (empty tangent vectors).
 struct NoDir {
+    static constexpr int width = 0;
     template <int ID>
-    AD_FN Zero seed() const { return {}; }
+    AD_FN TV<> seed() const { return {}; }
 };
 
-// Unit direction e_{BASE+K}: seed 1 on leaf BASE+K, Zero elsewhere.
-template <int K, int BASE = 0>
-struct UnitDir {
+// The N unit directions of leaves BASE .. BASE+N-1, all at once.
+template <int N, int BASE = 0>
+struct UnitDirs {
+    static constexpr int width = N;
     template <int ID>
     AD_FN auto seed() const {
-        if constexpr (ID == BASE + K)
-            return 1.0;
+        if constexpr (ID >= BASE && ID < BASE + N)
+            return unit_tv<N, ID - BASE>();
         else
-            return Zero{};
+            return Zeros<N>{};
     }
 };
 
-// Runtime direction on leaves BASE .. BASE+N-1, Zero elsewhere.
+// One runtime direction d on leaves BASE .. BASE+N-1.
 template <int N, int BASE = 0>
 struct VecDir {
+    static constexpr int width = 1;
     double d[N];
     template <int ID>
     AD_FN auto seed() const {
         if constexpr (ID >= BASE && ID < BASE + N)
-            return d[ID - BASE];
+            return TV<double>{d[ID - BASE], TV<>{}};
         else
-            return Zero{};
+            return Zeros<1>{};
     }
 };
 
@@ -116,37 +209,53 @@ struct Grad {
         for (int i = 0; i < N; ++i) g[i] = 0.0;
     }
     template <int ID, class B, class BT>
-    AD_FN void acc(B bv, BT) {
+    AD_FN void acc(B bv, const BT &) {
         if constexpr (ID >= BASE && ID < BASE + N) g[ID - BASE] += bv;
     }
 };
 
-// Tangents of the adjoints (Hessian-vector products) of leaves
-// BASE .. BASE+N-1.
+// Adjoint tangents of leaves BASE .. BASE+N-1 for a one-direction sweep
+// (a Hessian-vector product), optionally with the first-order adjoints.
 template <int N, int BASE = 0>
 struct GradT {
-    double g[N];
+    double g[N];   // tangent of the adjoint
+    double g1[N];  // first-order adjoint
     AD_FN GradT() {
-        for (int i = 0; i < N; ++i) g[i] = 0.0;
+        for (int i = 0; i < N; ++i) g[i] = g1[i] = 0.0;
     }
     template <int ID, class B, class BT>
-    AD_FN void acc(B, BT bt) {
-        if constexpr (ID >= BASE && ID < BASE + N) g[ID - BASE] += bt;
+    AD_FN void acc(B bv, const BT &bt) {
+        if constexpr (ID >= BASE && ID < BASE + N) {
+            g[ID - BASE] += bt.h;
+            g1[ID - BASE] += bv;
+        }
     }
 };
 
-// Both at once.
-template <int N, int BASE = 0>
-struct Grad2 {
-    double g[N], h[N];
-    AD_FN Grad2() {
-        for (int i = 0; i < N; ++i) g[i] = h[i] = 0.0;
+// Rows of a Hessian block: leaves BASE .. BASE+N-1 times the W directions
+// of the sweep, plus the first-order adjoints.
+template <int N, int W, int BASE = 0>
+struct HessRows {
+    double H[N][W];
+    double g[N];
+    AD_FN HessRows() {
+        for (int i = 0; i < N; ++i) {
+            g[i] = 0.0;
+            for (int j = 0; j < W; ++j) H[i][j] = 0.0;
+        }
+    }
+    template <int I, int J, class... Ts>
+    AD_FN void put(const TV<Ts...> &bt) {
+        if constexpr (J < W) {
+            H[I][J] += get<J>(bt);
+            put<I, J + 1>(bt);
+        }
     }
     template <int ID, class B, class BT>
-    AD_FN void acc(B bv, BT bt) {
+    AD_FN void acc(B bv, const BT &bt) {
         if constexpr (ID >= BASE && ID < BASE + N) {
             g[ID - BASE] += bv;
-            h[ID - BASE] += bt;
+            put<ID - BASE, 0>(bt);
         }
     }
 };
@@ -165,29 +274,29 @@ struct is_expr : std::is_base_of<Expr<T>, T> {};
 // Active leaf with compile-time id.
 template <int ID>
 struct Var : Expr<Var<ID>> {
-    static constexpr bool is_leaf = true;
     double val;
     AD_FN Var() : val(0.0) {}
     AD_FN explicit Var(double x) : val(x) {}
+    AD_FN void prep() const {}
     AD_FN double v() const { return val; }
     template <class Dir>
     AD_FN auto t(const Dir &d) const { return d.template seed<ID>(); }
     template <class Adj, class Dir, class B, class BT>
-    AD_FN void back(Adj &adj, const Dir &, B bv, BT bt) const {
+    AD_FN void back(Adj &adj, const Dir &, B bv, const BT &bt) const {
         adj.template acc<ID>(bv, bt);
     }
 };
 
 // Passive constant (stored by value).
 struct Cst : Expr<Cst> {
-    static constexpr bool is_leaf = false;
     double val;
     AD_FN explicit Cst(double x) : val(x) {}
+    AD_FN void prep() const {}
     AD_FN double v() const { return val; }
     template <class Dir>
-    AD_FN Zero t(const Dir &) const { return {}; }
+    AD_FN auto t(const Dir &) const { return Zeros<Dir::width>{}; }
     template <class Adj, class Dir, class B, class BT>
-    AD_FN void back(Adj &, const Dir &, B, BT) const {}
+    AD_FN void back(Adj &, const Dir &, B, const BT &) const {}
 };
 
 template <class T>
@@ -203,7 +312,6 @@ struct leaf_trait<Var<ID>> {
 template <class T>
 using Store = std::conditional_t<leaf_trait<T>::value, const T &, const T>;
 
-// wrap a double operand into a constant node
 template <class T>
 AD_FN decltype(auto) as_expr(const T &x) {
     if constexpr (std::is_arithmetic_v<T>)
@@ -222,11 +330,15 @@ struct Add : Expr<Add<L, R>> {
     Store<L> l;
     Store<R> r;
     AD_FN Add(const L &a, const R &b) : l(a), r(b) {}
+    AD_FN void prep() const {
+        l.prep();
+        r.prep();
+    }
     AD_FN double v() const { return l.v() + r.v(); }
     template <class Dir>
     AD_FN auto t(const Dir &d) const { return l.t(d) + r.t(d); }
     template <class Adj, class Dir, class B, class BT>
-    AD_FN void back(Adj &adj, const Dir &d, B bv, BT bt) const {
+    AD_FN void back(Adj &adj, const Dir &d, B bv, const BT &bt) const {
         l.back(adj, d, bv, bt);
         r.back(adj, d, bv, bt);
     }
@@ -237,55 +349,64 @@ struct Sub : Expr<Sub<L, R>> {
     Store<L> l;
     Store<R> r;
     AD_FN Sub(const L &a, const R &b) : l(a), r(b) {}
+    AD_FN void prep() const {
+        l.prep();
+        r.prep();
+    }
     AD_FN double v() const { return l.v() - r.v(); }
     template <class Dir>
     AD_FN auto t(const Dir &d) const { return l.t(d) - r.t(d); }
     template <class Adj, class Dir, class B, class BT>
-    AD_FN void back(Adj &adj, const Dir &d, B bv, BT bt) const {
+    AD_FN void back(Adj &adj, const Dir &d, B bv, const BT &bt) const {
         l.back(adj, d, bv, bt);
         r.back(adj, d, -bv, -bt);
     }
 };
 
-// d(lr) = r dl + l dr; second order: d2/dl dr = 1
+// d(lr) = r dl + l dr; the only second derivative is d2/dl dr = 1
 template <class L, class R>
 struct Mul : Expr<Mul<L, R>> {
     Store<L> l;
     Store<R> r;
     AD_FN Mul(const L &a, const R &b) : l(a), r(b) {}
+    AD_FN void prep() const {
+        l.prep();
+        r.prep();
+    }
     AD_FN double v() const { return l.v() * r.v(); }
     template <class Dir>
     AD_FN auto t(const Dir &d) const { return l.t(d) * r.v() + l.v() * r.t(d); }
     template <class Adj, class Dir, class B, class BT>
-    AD_FN void back(Adj &adj, const Dir &d, B bv, BT bt) const {
+    AD_FN void back(Adj &adj, const Dir &d, B bv, const BT &bt) const {
         const double lv = l.v(), rv = r.v();
         l.back(adj, d, bv * rv, bt * rv + bv * r.t(d));
         r.back(adj, d, bv * lv, bt * lv + bv * l.t(d));
     }
 };
 
-// d(l/r) = dl / r - l dr / r^2
+// q = l / r: dq = (dl - q dr) / r; partials 1/r and -q/r with tangents
+// -dr/r^2 and -(dl - 2 q dr)/r^2. The reciprocal is kept from prep().
 template <class L, class R>
 struct Div : Expr<Div<L, R>> {
     Store<L> l;
     Store<R> r;
-    AD_FN Div(const L &a, const R &b) : l(a), r(b) {}
-    AD_FN double v() const { return l.v() / r.v(); }
-    template <class Dir>
-    AD_FN auto t(const Dir &d) const {
-        const double ir = 1.0 / r.v();
-        return (l.t(d) - (l.v() * ir) * r.t(d)) * ir;
+    mutable double ir;
+    AD_FN Div(const L &a, const R &b) : l(a), r(b), ir(0.0) {}
+    AD_FN void prep() const {
+        l.prep();
+        r.prep();
+        ir = fm::rcp(r.v());
     }
+    AD_FN double v() const { return l.v() * ir; }
+    template <class Dir>
+    AD_FN auto t(const Dir &d) const { return (l.t(d) - (l.v() * ir) * r.t(d)) * ir; }
     template <class Adj, class Dir, class B, class BT>
-    AD_FN void back(Adj &adj, const Dir &d, B bv, BT bt) const {
-        const double ir = 1.0 / r.v();
-        const double q = l.v() * ir;               // the quotient
+    AD_FN void back(Adj &adj, const Dir &d, B bv, const BT &bt) const {
+        const double q = l.v() * ir;
         auto lt = l.t(d);
         auto rt = r.t(d);
-        auto qt = (lt - q * rt) * ir;              // tangent of the quotient
-        // d/dl = 1/r, d/dr = -q/r; their tangents -rt/r^2 and -(qt r - q rt)/r^2
         l.back(adj, d, bv * ir, bt * ir - bv * (rt * (ir * ir)));
-        r.back(adj, d, bv * (-q * ir), bt * (-q * ir) - bv * ((qt - q * ir * rt) * ir));
+        r.back(adj, d, bv * (-q * ir), bt * (-q * ir) - bv * ((lt - (2.0 * q) * rt) * (ir * ir)));
     }
 };
 
@@ -296,11 +417,12 @@ template <class A>
 struct Neg : Expr<Neg<A>> {
     Store<A> a;
     AD_FN explicit Neg(const A &x) : a(x) {}
+    AD_FN void prep() const { a.prep(); }
     AD_FN double v() const { return -a.v(); }
     template <class Dir>
     AD_FN auto t(const Dir &d) const { return -a.t(d); }
     template <class Adj, class Dir, class B, class BT>
-    AD_FN void back(Adj &adj, const Dir &d, B bv, BT bt) const {
+    AD_FN void back(Adj &adj, const Dir &d, B bv, const BT &bt) const {
         a.back(adj, d, -bv, -bt);
     }
 };
@@ -310,6 +432,7 @@ template <class A>
 struct Square : Expr<Square<A>> {
     Store<A> a;
     AD_FN explicit Square(const A &x) : a(x) {}
+    AD_FN void prep() const { a.prep(); }
     AD_FN double v() const {
         const double x = a.v();
         return x * x;
@@ -317,9 +440,9 @@ struct Square : Expr<Square<A>> {
     template <class Dir>
     AD_FN auto t(const Dir &d) const { return (2.0 * a.v()) * a.t(d); }
     template <class Adj, class Dir, class B, class BT>
-    AD_FN void back(Adj &adj, const Dir &d, B bv, BT bt) const {
-        const double x = a.v();
-        a.back(adj, d, bv * (2.0 * x), bt * (2.0 * x) + (2.0 * bv) * a.t(d));
+    AD_FN void back(Adj &adj, const Dir &d, B bv, const BT &bt) const {
+        const double x2 = 2.0 * a.v();
+        a.back(adj, d, bv * x2, bt * x2 + (2.0 * bv) * a.t(d));
     }
 };
 
@@ -329,21 +452,22 @@ struct Square : Expr<Square<A>> {
 template <class A>
 struct Sqrt : Expr<Sqrt<A>> {
     Store<A> a;
-    AD_FN explicit Sqrt(const A &x) : a(x) {}
-    AD_FN double v() const { return ::sqrt(a.v()); }
-    template <class Dir>
-    AD_FN auto t(const Dir &d) const {
-        const double y = ::sqrt(a.v());
-        const double c = y > 0.0 ? 0.5 / y : 0.0;
-        return c * a.t(d);
+    mutable double y, iy;
+    AD_FN explicit Sqrt(const A &x) : a(x), y(0.0), iy(0.0) {}
+    AD_FN void prep() const {
+        a.prep();
+        const double x = a.v();
+        const double r = x > 0.0 ? fm::rsqrt(x) : 0.0;
+        y = x * r;
+        iy = r;
     }
+    AD_FN double v() const { return y; }
+    template <class Dir>
+    AD_FN auto t(const Dir &d) const { return (0.5 * iy) * a.t(d); }
     template <class Adj, class Dir, class B, class BT>
-    AD_FN void back(Adj &adj, const Dir &d, B bv, BT bt) const {
-        const double y = ::sqrt(a.v());
-        const double iy = y > 0.0 ? 1.0 / y : 0.0;
-        const double c = 0.5 * iy;                 // dy/dx
-        auto ct = (-0.25 * iy * iy * iy) * a.t(d); // tangent of dy/dx
-        a.back(adj, d, bv * c, bt * c + bv * ct);
+    AD_FN void back(Adj &adj, const Dir &d, B bv, const BT &bt) const {
+        const double c = 0.5 * iy;
+        a.back(adj, d, bv * c, bt * c + (bv * (-0.25 * iy * iy * iy)) * a.t(d));
     }
 };
 
@@ -352,6 +476,7 @@ template <class A>
 struct Pos : Expr<Pos<A>> {
     Store<A> a;
     AD_FN explicit Pos(const A &x) : a(x) {}
+    AD_FN void prep() const { a.prep(); }
     AD_FN double v() const {
         const double x = a.v();
         return x > 0.0 ? x : 0.0;
@@ -359,7 +484,7 @@ struct Pos : Expr<Pos<A>> {
     template <class Dir>
     AD_FN auto t(const Dir &d) const { return keep_if(a.v() > 0.0, a.t(d)); }
     template <class Adj, class Dir, class B, class BT>
-    AD_FN void back(Adj &adj, const Dir &d, B bv, BT bt) const {
+    AD_FN void back(Adj &adj, const Dir &d, B bv, const BT &bt) const {
         const bool on = a.v() > 0.0;
         a.back(adj, d, keep_if(on, bv), keep_if(on, bt));
     }
@@ -368,13 +493,17 @@ struct Pos : Expr<Pos<A>> {
 template <class A>
 struct Exp : Expr<Exp<A>> {
     Store<A> a;
-    AD_FN explicit Exp(const A &x) : a(x) {}
-    AD_FN double v() const { return ::exp(a.v()); }
+    mutable double y;
+    AD_FN explicit Exp(const A &x) : a(x), y(0.0) {}
+    AD_FN void prep() const {
+        a.prep();
+        y = fm::exp(a.v());
+    }
+    AD_FN double v() const { return y; }
     template <class Dir>
-    AD_FN auto t(const Dir &d) const { return ::exp(a.v()) * a.t(d); }
+    AD_FN auto t(const Dir &d) const { return y * a.t(d); }
     template <class Adj, class Dir, class B, class BT>
-    AD_FN void back(Adj &adj, const Dir &d, B bv, BT bt) const {
-        const double y = ::exp(a.v());
+    AD_FN void back(Adj &adj, const Dir &d, B bv, const BT &bt) const {
         a.back(adj, d, bv * y, bt * y + (bv * y) * a.t(d));
     }
 };
@@ -382,13 +511,18 @@ struct Exp : Expr<Exp<A>> {
 template <class A>
 struct Log : Expr<Log<A>> {
     Store<A> a;
-    AD_FN explicit Log(const A &x) : a(x) {}
-    AD_FN double v() const { return ::log(a.v()); }
+    mutable double y, ix;
+    AD_FN explicit Log(const A &x) : a(x), y(0.0), ix(0.0) {}
+    AD_FN void prep() const {
+        a.prep();
+        y = fm::log(a.v());
+        ix = fm::rcp(a.v());
+    }
+    AD_FN double v() const { return y; }
     template <class Dir>
-    AD_FN auto t(const Dir &d) const { return a.t(d) / a.v(); }
+    AD_FN auto t(const Dir &d) const { return ix * a.t(d); }
     template <class Adj, class Dir, class B, class BT>
-    AD_FN void back(Adj &adj, const Dir &d, B bv, BT bt) const {
-        const double ix = 1.0 / a.v();
+    AD_FN void back(Adj &adj, const Dir &d, B bv, const BT &bt) const {
         a.back(adj, d, bv * ix, bt * ix - (bv * ix * ix) * a.t(d));
     }
 };
@@ -403,48 +537,39 @@ template <class U, class P>
 struct Pow : Expr<Pow<U, P>> {
     Store<U> u;
     Store<P> p;
-    AD_FN Pow(const U &a, const P &b) : u(a), p(b) {}
-
-    struct Partials {
-        double y, yu, yp, yuu, yup, ypp;
-    };
-    AD_FN static Partials partials(double uv, double pv) {
-        Partials r;
+    mutable double y, yu, yp, yuu, yup, ypp;
+    AD_FN Pow(const U &a, const P &b) : u(a), p(b), y(0), yu(0), yp(0), yuu(0), yup(0), ypp(0) {}
+    AD_FN void prep() const {
+        u.prep();
+        p.prep();
+        const double uv = u.v(), pv = p.v();
         if (uv > 0.0) {
-            const double lu = ::log(uv);
-            const double iu = 1.0 / uv;
-            r.y = ::exp(pv * lu);
-            r.yu = pv * r.y * iu;
-            r.yp = r.y * lu;
-            r.yuu = (pv - 1.0) * r.yu * iu;
-            r.yup = r.yu * lu + r.y * iu;
-            r.ypp = r.yp * lu;
+            const double lu = fm::log(uv);
+            const double iu = fm::rcp(uv);
+            y = fm::exp(pv * lu);
+            yu = pv * y * iu;
+            yp = y * lu;
+            yuu = (pv - 1.0) * yu * iu;
+            yup = yu * lu + y * iu;
+            ypp = yp * lu;
         } else {
-            r.y = 0.0;
-            r.yp = 0.0;
-            r.yu = pv == 1.0 ? 1.0 : 0.0;
-            r.yuu = pv == 2.0 ? 2.0 : 0.0;
-            r.yup = 0.0;
-            r.ypp = 0.0;
+            y = 0.0;
+            yp = 0.0;
+            yu = pv == 1.0 ? 1.0 : 0.0;
+            yuu = pv == 2.0 ? 2.0 : 0.0;
+            yup = 0.0;
+            ypp = 0.0;
         }
-        return r;
     }
-    AD_FN double v() const {
-        const double uv = u.v();
-        return uv > 0.0 ? ::exp(p.v() * ::log(uv)) : 0.0;
-    }
+    AD_FN double v() const { return y; }
     template <class Dir>
-    AD_FN auto t(const Dir &d) const {
-        const Partials r = partials(u.v(), p.v());
-        return r.yu * u.t(d) + r.yp * p.t(d);
-    }
+    AD_FN auto t(const Dir &d) const { return yu * u.t(d) + yp * p.t(d); }
     template <class Adj, class Dir, class B, class BT>
-    AD_FN void back(Adj &adj, const Dir &d, B bv, BT bt) const {
-        const Partials r = partials(u.v(), p.v());
+    AD_FN void back(Adj &adj, const Dir &d, B bv, const BT &bt) const {
         auto ut = u.t(d);
         auto pt = p.t(d);
-        u.back(adj, d, bv * r.yu, bt * r.yu + bv * (r.yuu * ut + r.yup * pt));
-        p.back(adj, d, bv * r.yp, bt * r.yp + bv * (r.yup * ut + r.ypp * pt));
+        u.back(adj, d, bv * yu, bt * yu + bv * (yuu * ut + yup * pt));
+        p.back(adj, d, bv * yp, bt * yp + bv * (yup * ut + ypp * pt));
     }
 };
 
@@ -487,52 +612,53 @@ AD_UNARY(log, Log)
 // drivers
 // --------------------------------------------------------------------------
 
-// Value and first-order adjoints (seed 1 at the root).
-template <class E, class Adj>
-AD_FN double value_grad(const E &e, Adj &adj) {
-    e.back(adj, NoDir{}, 1.0, Zero{});
+// Value only.
+template <class E>
+AD_FN double value(const E &e) {
+    e.prep();
     return e.v();
 }
 
-// Adjoint tangents in direction d: accumulates (Hessian . d) into adj.
+// Value and first-order adjoints (seed 1 at the root).
+template <class E, class Adj>
+AD_FN double value_grad(const E &e, Adj &adj) {
+    e.prep();
+    e.back(adj, NoDir{}, 1.0, TV<>{});
+    return e.v();
+}
+
+// Forward-over-reverse sweep in the directions of d: the accumulator
+// receives first-order adjoints and their tangents (Hessian times the
+// direction vectors). Returns the value.
 template <class E, class Dir, class Adj>
-AD_FN void hess_vec(const E &e, const Dir &d, Adj &adj) {
-    e.back(adj, d, 1.0, Zero{});
+AD_FN double sweep2(const E &e, const Dir &d, Adj &adj) {
+    e.prep();
+    e.back(adj, d, 1.0, Zeros<Dir::width>{});
+    return e.v();
 }
 
-// Directional derivative (forward tangent) of the value.
-template <class E, class Dir>
-AD_FN double tangent(const E &e, const Dir &d) {
-    auto t = e.t(d);
-    if constexpr (is_zero_v<decltype(t)>)
-        return 0.0;
-    else
-        return t;
-}
-
-// Hessian block d2 e / (d x_{ROW+i} d x_{COL+j}), i, j < N, by N unit
-// passes. Column j of the block is one Hessian-vector product.
-template <int N, int ROW, int COL, class E, int J = 0>
-AD_FN void hessian_block(const E &e, double (&H)[N][N]) {
-    if constexpr (J < N) {
-        GradT<N, ROW> acc;
-        hess_vec(e, UnitDir<J, COL>{}, acc);
-        for (int i = 0; i < N; ++i) H[i][J] = acc.g[i];
-        hessian_block<N, ROW, COL, E, J + 1>(e, H);
-    }
-}
-
-// Lower triangle (packed row-major: (i, j), j <= i at i (i + 1) / 2 + j) of
-// a symmetric Hessian block over leaves BASE .. BASE+5.
-template <int BASE, class E, int J = 0>
-AD_FN void hessian_sym6(const E &e, double (&Hp)[21]) {
-    if constexpr (J < 6) {
-        GradT<6, BASE> acc;
-        hess_vec(e, UnitDir<J, BASE>{}, acc);
+// Value, gradient and packed lower-triangular Hessian (entry (i, j), j <= i,
+// at i (i + 1) / 2 + j) over the six leaves BASE .. BASE+5, in one sweep.
+template <int BASE, class E>
+AD_FN double value_grad_hess6(const E &e, double *g, double *Hp) {
+    HessRows<6, 6, BASE> acc;
+    const double val = sweep2(e, UnitDirs<6, BASE>{}, acc);
 #pragma unroll
-        for (int i = J; i < 6; ++i) Hp[i * (i + 1) / 2 + J] = acc.g[i];
-        hessian_sym6<BASE, E, J + 1>(e, Hp);
+    for (int i = 0; i < 6; ++i) {
+        g[i] = acc.g[i];
+#pragma unroll
+        for (int j = 0; j <= i; ++j) Hp[i * (i + 1) / 2 + j] = acc.H[i][j];
     }
+    return val;
+}
+
+// Full block d2 e / (d x_{ROW+i} d x_{COL+j}) in one sweep.
+template <int ROW, int COL, class E>
+AD_FN void hessian_block6(const E &e, double (&H)[6][6]) {
+    HessRows<6, 6, ROW> acc;
+    sweep2(e, UnitDirs<6, COL>{}, acc);
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) H[i][j] = acc.H[i][j];
 }
 
 }  // namespace ad

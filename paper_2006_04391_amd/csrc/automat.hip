@@ -61,14 +61,23 @@ __device__ __forceinline__ void count_failures(unsigned long long *counter, bool
     }
 }
 
+// Keeps the compiler from hoisting LDS reads (per-phase constants, the
+// staged inputs) out of the Newton loop into registers: they are cheap to
+// re-read, and holding them would cost ~90 VGPRs and most of the occupancy.
+__device__ __forceinline__ void lds_reload_point() { asm volatile("" ::: "memory"); }
+
 template <bool TANGENT>
 __global__ __launch_bounds__(kBlock) void gsm_eval_kernel(const EvalArgs args) {
     extern __shared__ double smem_raw[];
-    PC *tab = reinterpret_cast<PC *>(smem_raw);
+    // per-lane staging of eps and a_n, component-major [12][kBlock]
+    double *stage = smem_raw;
+    PC *tab = reinterpret_cast<PC *>(smem_raw + 12 * kBlock);
     for (int k = threadIdx.x; k < args.n_phases; k += blockDim.x)
         build_phase_const<Model>(args.phases[k], tab[k], TANGENT);
     __syncthreads();
 
+    double *eps = stage + threadIdx.x;            // eps[c * kBlock]
+    double *an = stage + 6 * kBlock + threadIdx.x;  // an[c * kBlock]
     const int64_t n = args.n;
     const double h = args.h;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
@@ -76,14 +85,17 @@ __global__ __launch_bounds__(kBlock) void gsm_eval_kernel(const EvalArgs args) {
         const int64_t i = base + threadIdx.x;
         if (i >= n) continue;
 
-        double eps[6], an[6];
+        bool finite_in = true;
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-            eps[c] = __builtin_nontemporal_load(args.eps + c * n + i);
-            an[c] = __builtin_nontemporal_load(args.a_old + c * n + i);
+            const double e = __builtin_nontemporal_load(args.eps + c * n + i);
+            const double a = __builtin_nontemporal_load(args.a_old + c * n + i);
+            finite_in = finite_in && isfinite(e) && isfinite(a);
+            eps[c * kBlock] = e;
+            an[c * kBlock] = a;
         }
         const int pid = args.phase[i];
-        const bool valid = pid < args.n_phases && finite6(eps) && finite6(an);
+        const bool valid = pid < args.n_phases && finite_in;
         const PC &pc = tab[valid ? pid : 0];
         const Model::Phase &prm = pc.prm;
         const bool newton = valid && Model::flows(prm);
@@ -93,12 +105,13 @@ __global__ __launch_bounds__(kBlock) void gsm_eval_kernel(const EvalArgs args) {
         double phi = 0.0;
         int status = valid ? 0 : -1;
         if (newton) {
-            residual<Model>(prm, eps, an, D, h, cur);
+            residual<Model>(prm, Strided<kBlock>{eps}, Strided<kBlock>{an}, D, h, cur);
             phi = h * cur.psi;
         }
         bool done = !newton;
         int k = 0;
         for (;;) {
+            lds_reload_point();
             if (!done) {
                 bool zero = true;
 #pragma unroll
@@ -106,7 +119,8 @@ __global__ __launch_bounds__(kBlock) void gsm_eval_kernel(const EvalArgs args) {
                 bool conv = zero;
                 if (!conv && k >= 1) {
                     if (args.flags & AUTOMAT_SIGMA_CRITERION)
-                        conv = sigma_converged<Model>(prm, eps, an, D, cur.F, args.tol);
+                        conv = sigma_converged<Model>(prm, Strided<kBlock>{eps}, Strided<kBlock>{an},
+                                                      D, cur.F, args.tol);
                     else
                         conv = la::norm_inf6(cur.F) <= args.tol * la::norm_inf6(D);
                 }
@@ -143,9 +157,10 @@ __global__ __launch_bounds__(kBlock) void gsm_eval_kernel(const EvalArgs args) {
                     const double psi0 = cur.psi;
                     double t = 1.0, dphi, Dt[6];
                     for (;;) {
+                        lds_reload_point();
 #pragma unroll
                         for (int c = 0; c < 6; ++c) Dt[c] = D[c] - t * delta[c];
-                        residual<Model>(prm, eps, an, Dt, h, cur);
+                        residual<Model>(prm, Strided<kBlock>{eps}, Strided<kBlock>{an}, Dt, h, cur);
                         dphi = -t * s1 + 0.5 * t * t * s2 + h * (cur.psi - psi0);
                         if (dphi <= -1e-4 * t * slope + 1e-13 * phi || t < 0x1p-30) break;
                         t *= 0.5;
@@ -157,13 +172,17 @@ __global__ __launch_bounds__(kBlock) void gsm_eval_kernel(const EvalArgs args) {
                 }
             }
         }
+        lds_reload_point();
 
         // outputs
-        double sig[6], anew[6];
+        double sig[6], anew[6], epsv[6];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) anew[c] = newton ? an[c] + D[c] : an[c];
+        for (int c = 0; c < 6; ++c) {
+            anew[c] = newton ? an[c * kBlock] + D[c] : an[c * kBlock];
+            epsv[c] = eps[c * kBlock];
+        }
         if (valid) {
-            Model::stress(prm, eps, anew, sig);
+            Model::stress(prm, epsv, anew, sig);
         } else {
 #pragma unroll
             for (int c = 0; c < 6; ++c) sig[c] = anew[c] = NAN;
@@ -240,7 +259,7 @@ static int32_t device_info(DeviceInfo &out) {
         DeviceInfo d;
         if (hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             return AUTOMAT_EHIP;
-        const size_t smem = AUTOMAT_MAX_PHASES * sizeof(PC);
+        const size_t smem = 12 * kBlock * sizeof(double) + AUTOMAT_MAX_PHASES * sizeof(PC);
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&d.blocks_fwd, gsm_eval_kernel<false>,
                                                          kBlock, smem) != hipSuccess ||
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&d.blocks_tan, gsm_eval_kernel<true>,
@@ -283,6 +302,7 @@ int32_t copy_params(const automat_params *params, Model::Phase *dst, int32_t *n_
         const automat_phase &p = params->phase[k];
         if (!valid_phase(p)) return AUTOMAT_EINVAL;
         Model::Phase q;
+        std::memset(&q, 0, sizeof q);
         q.kind = p.kind;
         q.reserved = 0;
         q.E = p.E;
@@ -338,7 +358,7 @@ extern "C" int32_t automat_evaluate_ex(int64_t n, const double *eps_new, const d
     const int64_t tiles = (n + kBlock - 1) / kBlock;
     const int64_t cap = (int64_t)dev.cus * (tangent_out ? dev.blocks_tan : dev.blocks_fwd);
     const int grid = (int)(tiles < cap ? tiles : cap);
-    const size_t smem = (size_t)args.n_phases * sizeof(PC);
+    const size_t smem = 12 * kBlock * sizeof(double) + (size_t)args.n_phases * sizeof(PC);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (tangent_out)
         hipLaunchKernelGGL(gsm_eval_kernel<true>, dim3(grid), dim3(kBlock), smem, s, args);

@@ -1,0 +1,140 @@
+// fastmath.hpp -- FP64 reciprocal, reciprocal square root, log and exp for
+// the hot path, accurate to a few units in the last place (not correctly
+// rounded). The material-point solve needs its transcendental results to
+// about 1e-14 relative, far inside the 1e-10 parity bar, but calls them in
+// every Newton residual, so the general-purpose library sequences (which
+// also handle every special case and round correctly) dominate the
+// instruction count.
+//
+// Methods (textbook, written from the mathematics):
+//  * rcp / rsqrt: the hardware estimate (v_rcp_f64 / v_rsq_f64) refined by
+//    two Newton-Raphson steps, r <- r + r (1 - x r) and
+//    r <- r + r/2 (1 - x r^2);
+//  * log: x = 2^k m with m in [sqrt(1/2), sqrt(2)), s = (m - 1)/(m + 1),
+//    log m = 2 atanh s = 2 (s + s^3/3 + s^5/5 + ...) summed to s^23
+//    (|s| <= 0.1716, truncation < 1e-17), log x = k ln2 + log m with ln2
+//    split in a high and a low part;
+//  * exp: x = k ln2 + r, k = rint(x / ln2), |r| <= ln2/2, exp r by its
+//    Taylor series to r^13 (truncation < 5e-18), scaled by 2^k.
+// Domain: rcp, rsqrt for finite x > 0; log for finite x > 0 (subnormal x
+// handled by a pre-scale); exp for any x (underflow to 0, overflow to inf).
+// Host and device run the same refinement and polynomial code; only the
+// initial estimate of rcp / rsqrt differs (hardware on the device, a
+// single-precision estimate on the host), which the refinement removes to
+// within an ulp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#ifndef AD_FN
+#define AD_FN __host__ __device__ __forceinline__
+#endif
+
+namespace automat {
+namespace fm {
+
+// Polynomial coefficients and reduction constants live in a small mutable
+// table rather than in the instruction stream: the compiler then loads them
+// (uniform scalar loads) where they are used instead of materializing all of
+// them once per kernel and holding them in ~50 vector registers.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define AUTOMAT_FM_TABLE static __device__
+#else
+#define AUTOMAT_FM_TABLE static
+#endif
+// [0..10] 1/23, 1/21, ..., 1/3 (log series); [11..24] 1/13!, ..., 1/1!, 1
+// (exp series); [25] ln2 high part, [26] ln2 low part, [27] 1/ln2,
+// [28] sqrt(1/2)
+AUTOMAT_FM_TABLE double fm_tab[29] = {
+    1.0 / 23.0, 1.0 / 21.0, 1.0 / 19.0, 1.0 / 17.0, 1.0 / 15.0, 1.0 / 13.0, 1.0 / 11.0,
+    1.0 / 9.0, 1.0 / 7.0, 1.0 / 5.0, 1.0 / 3.0,
+    1.0 / 6227020800.0, 1.0 / 479001600.0, 1.0 / 39916800.0, 1.0 / 3628800.0,
+    1.0 / 362880.0, 1.0 / 40320.0, 1.0 / 5040.0, 1.0 / 720.0, 1.0 / 120.0, 1.0 / 24.0,
+    1.0 / 6.0, 0.5, 1.0, 1.0,
+    0x1.62e42fefa3800p-1, 0x1.ef35793c76730p-45, 1.4426950408889634074,
+    0.70710678118654752440};
+
+AD_FN double rcp_estimate(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcp(x);
+#else
+    int k;
+    const double m = ::frexp(x, &k);  // keep the float estimate in range
+    return ::ldexp((double)(1.0f / (float)m), -k);
+#endif
+}
+
+AD_FN double rsq_estimate(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rsq(x);
+#else
+    int k;
+    double m = ::frexp(x, &k);
+    if (k & 1) {
+        m *= 2.0;
+        k -= 1;
+    }
+    return ::ldexp((double)(1.0f / ::sqrtf((float)m)), -k / 2);
+#endif
+}
+
+// 1 / x for finite x != 0
+AD_FN double rcp(double x) {
+    double r = rcp_estimate(x);
+    double e = ::fma(-x, r, 1.0);
+    r = ::fma(r, e, r);
+    e = ::fma(-x, r, 1.0);
+    return ::fma(r, e, r);
+}
+
+// 1 / sqrt(x) for finite x > 0
+AD_FN double rsqrt(double x) {
+    double r = rsq_estimate(x);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double e = ::fma(-x, r * r, 1.0);
+        r = ::fma(0.5 * r, e, r);
+    }
+    return r;
+}
+
+// natural logarithm for finite x > 0
+AD_FN double log(double x) {
+    const double *T = fm_tab;
+    const bool tiny = x < 0x1p-1000;
+    if (tiny) x *= 0x1p+200;
+    int k;
+    double m = ::frexp(x, &k);            // x = m 2^k, m in [0.5, 1)
+    if (m < T[28]) {                      // move m to [sqrt(1/2), sqrt(2))
+        m *= 2.0;
+        k -= 1;
+    }
+    const double s = (m - 1.0) * rcp(m + 1.0);
+    const double z = s * s;
+    // 2 atanh(s) = 2 s (1 + z/3 + z^2/5 + ... + z^11/23)
+    double p = T[0];
+#pragma unroll
+    for (int j = 1; j <= 10; ++j) p = ::fma(p, z, T[j]);
+    const double lm = ::fma(2.0 * s * z, p, 2.0 * s);
+    const double kd = (double)(tiny ? k - 200 : k);
+    return ::fma(kd, T[25], ::fma(kd, T[26], lm));
+}
+
+// exponential
+AD_FN double exp(double x) {
+    const double *T = fm_tab;
+    if (x < -745.2) return 0.0;
+    if (x > 709.8) return HUGE_VAL;
+    const double kd = ::rint(x * T[27]);
+    const double r = ::fma(-kd, T[26], ::fma(-kd, T[25], x));
+    // Taylor series of e^r to r^13, Horner form
+    double p = T[11];
+#pragma unroll
+    for (int j = 12; j <= 24; ++j) p = ::fma(p, r, T[j]);
+    return ::ldexp(p, (int)kd);
+}
+
+}  // namespace fm
+}  // namespace automat

@@ -57,8 +57,9 @@ template <class Model>
 AD_FN bool build_phase_const(const typename Model::Phase &p, PhaseConst<Model> &pc,
                              bool tangent) {
     pc.prm = p;
+    Model::derive(pc.prm);
     double Kaa[21], Kae[6][6], Kee[21];
-    Model::omega_hessian(p, Kaa, Kae, Kee);
+    Model::omega_hessian(pc.prm, Kaa, Kae, Kee);
     double L[21], idg[6];
 #pragma unroll
     for (int i = 0; i < 21; ++i) {
@@ -99,19 +100,30 @@ AD_FN bool build_phase_const(const typename Model::Phase &p, PhaseConst<Model> &
     return ok;
 }
 
+// Read-only view of a 6-vector stored with a stride (e.g. a lane's column of
+// an LDS staging array); plain arrays work too.
+template <int S>
+struct Strided {
+    const double *p;
+    AD_FN double operator[](int i) const { return p[i * S]; }
+};
+
 // State of one residual evaluation: generalized stress, residual, Psi.
 struct Resid {
     double A[6], F[6];
     double psi;
 };
 
-template <class Model>
-AD_FN void residual(const typename Model::Phase &prm, const double *eps, const double *an,
+template <class Model, class V>
+AD_FN void residual(const typename Model::Phase &prm, const V &eps, const V &an,
                     const double *D, double h, Resid &r) {
-    double a[6], f[6];
+    double a[6], e[6], f[6];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) a[i] = an[i] + D[i];
-    Model::gen_stress(prm, eps, a, r.A);
+    for (int i = 0; i < 6; ++i) {
+        a[i] = an[i] + D[i];
+        e[i] = eps[i];
+    }
+    Model::gen_stress(prm, e, a, r.A);
     r.psi = Model::psi_grad(prm, r.A, f);
 #pragma unroll
     for (int i = 0; i < 6; ++i) r.F[i] = D[i] - h * f[i];
@@ -119,12 +131,15 @@ AD_FN void residual(const typename Model::Phase &prm, const double *eps, const d
 
 // Stress-criterion test: ||d sigma / d a . F||_inf <= tol ||sigma||_inf at
 // a = a_n + D, with both terms from the AD layer.
-template <class Model>
-AD_FN bool sigma_converged(const typename Model::Phase &prm, const double *eps,
-                           const double *an, const double *D, const double *F, double tol) {
-    double a[6], sig[6];
+template <class Model, class V>
+AD_FN bool sigma_converged(const typename Model::Phase &prm, const V &epsv, const V &an,
+                           const double *D, const double *F, double tol) {
+    double a[6], sig[6], eps[6];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) a[i] = an[i] + D[i];
+    for (int i = 0; i < 6; ++i) {
+        a[i] = an[i] + D[i];
+        eps[i] = epsv[i];
+    }
     Model::stress(prm, eps, a, sig);
     Leaves6<Model::OM_EPS> le(eps);
     Leaves6<Model::OM_A> la_(a);
@@ -132,7 +147,7 @@ AD_FN bool sigma_converged(const typename Model::Phase &prm, const double *eps,
 #pragma unroll
     for (int i = 0; i < 6; ++i) dir.d[i] = F[i];
     ad::GradT<6, Model::OM_EPS> dsig;
-    ad::hess_vec(Model::omega(le, la_, prm.E, prm.nu, prm.H), dir, dsig);
+    ad::sweep2(Model::omega(le, la_, prm.lam, prm.mu, prm.H), dir, dsig);
     return la::norm_inf6(dsig.g) <= tol * la::norm_inf6(sig);
 }
 

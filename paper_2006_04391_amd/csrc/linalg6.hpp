@@ -23,9 +23,8 @@ AD_FN bool cholesky6(double *L, double *idg) {
 #pragma unroll
         for (int k = 0; k < j; ++k) d -= L[pk(j, k)] * L[pk(j, k)];
         ok = ok && (d > 0.0);
-        const double ljj = ::sqrt(d);
-        const double inv = 1.0 / ljj;
-        L[pk(j, j)] = ljj;
+        const double inv = fm::rsqrt(d);
+        L[pk(j, j)] = d * inv;
         idg[j] = inv;
 #pragma unroll
         for (int i = j + 1; i < 6; ++i) {

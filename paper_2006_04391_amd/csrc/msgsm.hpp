@@ -14,9 +14,12 @@
 //
 // Everything the solver needs is derived from these two scalar expressions
 // by the AD layer: A = -d omega / d a and sigma = d omega / d eps by reverse
-// sweeps, f = dPsi/dA by a reverse sweep, Psi'' and the Hessian blocks of
-// omega by forward-over-reverse passes, and parameter partials by passes
-// seeded on the parameter leaves.
+// sweeps, f = dPsi/dA and Psi'' by one forward-over-reverse sweep, the
+// Hessian blocks of omega likewise, and parameter partials by sweeps seeded
+// on the parameter leaves. The potentials are written once, over parameter
+// arguments that are plain numbers on the hot path (derived per phase: the
+// Lame constants, sigma0 eps0 / (n + 1), 1 / sigma0, n + 1) and expressions
+// of parameter leaves when parameter derivatives are wanted.
 #pragma once
 
 #include "ad.hpp"
@@ -45,11 +48,13 @@ struct Leaves6 {
 };
 
 struct MSGSM {
-    // Raw per-phase parameters, as in the ABI (kind 0 elastic, 1 flowing).
+    // Per-phase parameters: raw as in the ABI (kind 0 elastic, 1 flowing),
+    // then the derived constants filled by derive().
     struct Phase {
         int kind;
         int reserved;
         double E, nu, H, sy, s0, e0, n;
+        double lam, mu, coef, is0, pq;
     };
 
     // Leaf ids. omega: eps 0..5, a 6..11, E 12, nu 13, H 14.
@@ -57,12 +62,29 @@ struct MSGSM {
     static constexpr int OM_EPS = 0, OM_A = 6, OM_E = 12, OM_NU = 13, OM_H = 14;
     static constexpr int PS_A = 0, PS_SY = 6, PS_S0 = 7, PS_E0 = 8, PS_N = 9;
 
-    // The free energy. E, nu, H may be constants or leaves.
-    template <class EL, class AL, class TE, class TN, class TH>
-    AD_FN static auto omega(const EL &e, const AL &a, const TE &E, const TN &nu, const TH &H) {
+    template <class TE, class TN>
+    AD_FN static auto lame_lambda(const TE &E, const TN &nu) {
         using namespace ad;
-        auto lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
-        auto mu = E / (2.0 * (1.0 + nu));
+        return E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    }
+    template <class TE, class TN>
+    AD_FN static auto lame_mu(const TE &E, const TN &nu) {
+        using namespace ad;
+        return E / (2.0 * (1.0 + nu));
+    }
+
+    AD_FN static void derive(Phase &p) {
+        p.lam = lame_lambda(p.E, p.nu);
+        p.mu = lame_mu(p.E, p.nu);
+        p.coef = p.s0 * p.e0 / (p.n + 1.0);
+        p.is0 = 1.0 / p.s0;
+        p.pq = p.n + 1.0;
+    }
+
+    // The free energy over Lame constants lam, mu and hardening modulus H.
+    template <class EL, class AL, class TL, class TM, class TH>
+    AD_FN static auto omega(const EL &e, const AL &a, const TL &lam, const TM &mu, const TH &H) {
+        using namespace ad;
         auto e0 = e.c0 - a.c0;
         auto e1 = e.c1 - a.c1;
         auto e2 = e.c2 - a.c2;
@@ -89,21 +111,21 @@ struct MSGSM {
         return 0.5 * (sq(s0) + sq(s1) + sq(s2)) + sq(A.c3) + sq(A.c4) + sq(A.c5);
     }
 
-    // The force potential, handed to f(expr). Without a yield threshold the
-    // power of the equivalent stress is written as a power of 3 J2, which
-    // avoids the square root (and its cone point) altogether; with a
+    // The force potential over coef = sigma0 eps0 / (n + 1), is0 = 1 / sigma0,
+    // pq = n + 1 and sigma_y, handed to f(expr). Without a yield threshold
+    // the power of the equivalent stress is written as a power of 3 J2,
+    // which avoids the square root (and its cone point) altogether; with a
     // threshold the positive part of (q - sigma_y) is taken.
-    template <class AL, class TY, class T0, class TE, class TN, class F>
-    AD_FN static void with_psi(const AL &A, const TY &sy, const T0 &s0, const TE &e0,
-                               const TN &n, bool no_threshold, F &&f) {
+    template <class AL, class TY, class TC, class TI, class TP, class F>
+    AD_FN static void with_psi(const AL &A, const TY &sy, const TC &coef, const TI &is0,
+                               const TP &pq, bool no_threshold, F &&f) {
         using namespace ad;
-        auto coef = s0 * e0 / (n + 1.0);
         if (no_threshold) {
-            auto u = 3.0 * j2(A) / sq(s0);
-            f(coef * pow(u, 0.5 * (n + 1.0)));
+            auto u = 3.0 * j2(A) * sq(is0);
+            f(coef * pow(u, 0.5 * pq));
         } else {
-            auto x = pos(sqrt(3.0 * j2(A)) - sy);
-            f(coef * pow(x / s0, n + 1.0));
+            auto x = pos(sqrt(3.0 * j2(A)) - sy) * is0;
+            f(coef * pow(x, pq));
         }
     }
 
@@ -116,7 +138,7 @@ struct MSGSM {
         Leaves6<OM_EPS> le(eps);
         Leaves6<OM_A> la(a);
         ad::Grad<6, OM_A> g;
-        ad::value_grad(omega(le, la, p.E, p.nu, p.H), g);
+        ad::value_grad(omega(le, la, p.lam, p.mu, p.H), g);
 #pragma unroll
         for (int i = 0; i < 6; ++i) A[i] = -g.g[i];
     }
@@ -126,7 +148,7 @@ struct MSGSM {
         Leaves6<OM_EPS> le(eps);
         Leaves6<OM_A> la(a);
         ad::Grad<6, OM_EPS> g;
-        ad::value_grad(omega(le, la, p.E, p.nu, p.H), g);
+        ad::value_grad(omega(le, la, p.lam, p.mu, p.H), g);
 #pragma unroll
         for (int i = 0; i < 6; ++i) sig[i] = g.g[i];
     }
@@ -136,26 +158,24 @@ struct MSGSM {
         Leaves6<PS_A> la(A);
         double val = 0.0;
         ad::Grad<6, PS_A> g;
-        with_psi(la, p.sy, p.s0, p.e0, p.n, p.sy == 0.0,
+        with_psi(la, p.sy, p.coef, p.is0, p.pq, p.sy == 0.0,
                  [&](const auto &e) { val = ad::value_grad(e, g); });
 #pragma unroll
         for (int i = 0; i < 6; ++i) f[i] = g.g[i];
         return val;
     }
 
-    // Psi''(A), packed lower triangle
+    // Psi''(A), packed lower triangle, by one sweep
     AD_FN static void psi_hess(const Phase &p, const double *A, double *Hp) {
         Leaves6<PS_A> la(A);
-        double H[21];
-        with_psi(la, p.sy, p.s0, p.e0, p.n, p.sy == 0.0,
-                 [&](const auto &e) { ad::hessian_sym6<PS_A>(e, H); });
-#pragma unroll
-        for (int i = 0; i < 21; ++i) Hp[i] = H[i];
+        double g[6];
+        with_psi(la, p.sy, p.coef, p.is0, p.pq, p.sy == 0.0,
+                 [&](const auto &e) { ad::value_grad_hess6<PS_A>(e, g, Hp); });
     }
 
     // ---- second-order quantities for the vector-Jacobian product ----------
 
-    // Psi''(A) w by one forward-over-reverse pass (same form of Psi as the
+    // Psi''(A) w by one forward-over-reverse sweep (same form of Psi as the
     // Newton solve).
     AD_FN static void psi_hvp(const Phase &p, const double *A, const double *w, double *out) {
         Leaves6<PS_A> la(A);
@@ -163,14 +183,14 @@ struct MSGSM {
 #pragma unroll
         for (int i = 0; i < 6; ++i) dir.d[i] = w[i];
         ad::GradT<6, PS_A> acc;
-        with_psi(la, p.sy, p.s0, p.e0, p.n, p.sy == 0.0,
-                 [&](const auto &e) { ad::hess_vec(e, dir, acc); });
+        with_psi(la, p.sy, p.coef, p.is0, p.pq, p.sy == 0.0,
+                 [&](const auto &e) { ad::sweep2(e, dir, acc); });
 #pragma unroll
         for (int i = 0; i < 6; ++i) out[i] = acc.g[i];
     }
 
-    // d^2 omega/(d x d eps_j) . u for x in (eps, a): returns the eps part in
-    // ge and the a part in ga, i.e. (omega_ee u, omega_ae u).
+    // (omega_ee u, omega_ae u): the tangent of the gradient of omega in the
+    // direction u on eps.
     AD_FN static void omega_hvp_eps(const Phase &p, const double *eps, const double *a,
                                     const double *u, double *ge, double *ga) {
         Leaves6<OM_EPS> le(eps);
@@ -179,7 +199,7 @@ struct MSGSM {
 #pragma unroll
         for (int i = 0; i < 6; ++i) dir.d[i] = u[i];
         ad::GradT<12, OM_EPS> acc;
-        ad::hess_vec(omega(le, la, p.E, p.nu, p.H), dir, acc);
+        ad::sweep2(omega(le, la, p.lam, p.mu, p.H), dir, acc);
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
             ge[i] = acc.g[i];
@@ -188,7 +208,7 @@ struct MSGSM {
     }
 
     // With direction (u on eps, v on a) and E, nu, H as leaves:
-    // ge = d/deps (grad omega . (u, v)) and gp = d/d(E, nu, H) (grad omega . (u, v)).
+    // ge = d/deps (grad omega . (u, v)), gp = d/d(E, nu, H) (grad omega . (u, v)).
     AD_FN static void omega_hvp_params(const Phase &p, const double *eps, const double *a,
                                        const double *u, const double *v, double *ge,
                                        double *gp) {
@@ -204,7 +224,7 @@ struct MSGSM {
             dir.d[6 + i] = v[i];
         }
         ad::GradT<15, OM_EPS> acc;
-        ad::hess_vec(omega(le, la, E, nu, H), dir, acc);
+        ad::sweep2(omega(le, la, lame_lambda(E, nu), lame_mu(E, nu), H), dir, acc);
 #pragma unroll
         for (int i = 0; i < 6; ++i) ge[i] = acc.g[i];
         gp[0] = acc.g[OM_E];
@@ -217,16 +237,20 @@ struct MSGSM {
     // one at sigma_y = 0.
     AD_FN static void psi_param_partials(const Phase &p, const double *A, const double *w,
                                          double *gp) {
+        using namespace ad;
         Leaves6<PS_A> la(A);
-        ad::Var<PS_SY> sy(p.sy);
-        ad::Var<PS_S0> s0(p.s0);
-        ad::Var<PS_E0> e0(p.e0);
-        ad::Var<PS_N> n(p.n);
-        ad::VecDir<6, PS_A> dir;
+        Var<PS_SY> sy(p.sy);
+        Var<PS_S0> s0(p.s0);
+        Var<PS_E0> e0(p.e0);
+        Var<PS_N> n(p.n);
+        VecDir<6, PS_A> dir;
 #pragma unroll
         for (int i = 0; i < 6; ++i) dir.d[i] = w[i];
-        ad::GradT<4, PS_SY> acc;
-        with_psi(la, sy, s0, e0, n, false, [&](const auto &e) { ad::hess_vec(e, dir, acc); });
+        GradT<4, PS_SY> acc;
+        auto coef = s0 * e0 / (n + 1.0);
+        auto is0 = 1.0 / s0;
+        auto pq = n + 1.0;
+        with_psi(la, sy, coef, is0, pq, false, [&](const auto &e) { sweep2(e, dir, acc); });
 #pragma unroll
         for (int i = 0; i < 4; ++i) gp[i] = acc.g[i];
     }
@@ -239,15 +263,11 @@ struct MSGSM {
         const double z[6] = {0, 0, 0, 0, 0, 0};
         Leaves6<OM_EPS> le(z);
         Leaves6<OM_A> la(z);
-        auto om = omega(le, la, p.E, p.nu, p.H);
-        double a2[21], e2[21];
-        ad::hessian_sym6<OM_A>(om, a2);
-        ad::hessian_sym6<OM_EPS>(om, e2);
-        ad::hessian_block<6, OM_A, OM_EPS>(om, Kae);
-        for (int i = 0; i < 21; ++i) {
-            Kaa[i] = a2[i];
-            Kee[i] = e2[i];
-        }
+        auto om = omega(le, la, p.lam, p.mu, p.H);
+        double g[6];
+        ad::value_grad_hess6<OM_A>(om, g, Kaa);
+        ad::value_grad_hess6<OM_EPS>(om, g, Kee);
+        ad::hessian_block6<OM_A, OM_EPS>(om, Kae);
     }
 };
 
