@@ -66,8 +66,13 @@ __device__ __forceinline__ void count_failures(unsigned long long *counter, bool
 // re-read, and holding them would cost ~90 VGPRs and most of the occupancy.
 __device__ __forceinline__ void lds_reload_point() { asm volatile("" ::: "memory"); }
 
+#ifndef AUTOMAT_EVAL_WAVES
+#define AUTOMAT_EVAL_WAVES 3
+#endif
+
 template <bool TANGENT>
-__global__ __launch_bounds__(kBlock) void gsm_eval_kernel(const EvalArgs args) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(AUTOMAT_EVAL_WAVES)))
+void gsm_eval_kernel(const EvalArgs args) {
     extern __shared__ double smem_raw[];
     // per-lane staging of eps and a_n, component-major [12][kBlock]
     double *stage = smem_raw;
@@ -147,6 +152,7 @@ __global__ __launch_bounds__(kBlock) void gsm_eval_kernel(const EvalArgs args) {
                     for (int c = 0; c < 6; ++c) y[c] = cur.F[c];
                     la::chol_solve6(M, idg, y);
                 }
+                lds_reload_point();
                 if (!spd) {
                     done = true;
                     status = -1;
@@ -155,18 +161,20 @@ __global__ __launch_bounds__(kBlock) void gsm_eval_kernel(const EvalArgs args) {
                     const double slope = la::dot6(cur.F, y);
                     const double s1 = la::dot6(D, y), s2 = la::dot6(delta, y);
                     const double psi0 = cur.psi;
-                    double t = 1.0, dphi, Dt[6];
+                    // full step first; a rejected trial D - t delta moves to
+                    // D - t/2 delta = (D - t delta) + t/2 delta in place
+                    double t = 1.0, dphi;
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) D[c] -= delta[c];
                     for (;;) {
                         lds_reload_point();
-#pragma unroll
-                        for (int c = 0; c < 6; ++c) Dt[c] = D[c] - t * delta[c];
-                        residual<Model>(prm, Strided<kBlock>{eps}, Strided<kBlock>{an}, Dt, h, cur);
+                        residual<Model>(prm, Strided<kBlock>{eps}, Strided<kBlock>{an}, D, h, cur);
                         dphi = -t * s1 + 0.5 * t * t * s2 + h * (cur.psi - psi0);
                         if (dphi <= -1e-4 * t * slope + 1e-13 * phi || t < 0x1p-30) break;
                         t *= 0.5;
-                    }
 #pragma unroll
-                    for (int c = 0; c < 6; ++c) D[c] = Dt[c];
+                        for (int c = 0; c < 6; ++c) D[c] += t * delta[c];
+                    }
                     phi += dphi;
                     ++k;
                 }

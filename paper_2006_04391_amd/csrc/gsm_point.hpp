@@ -124,6 +124,7 @@ AD_FN void residual(const typename Model::Phase &prm, const V &eps, const V &an,
         e[i] = eps[i];
     }
     Model::gen_stress(prm, e, a, r.A);
+    asm volatile("" ::: "memory");  // re-read the phase constants for the Psi sweep
     r.psi = Model::psi_grad(prm, r.A, f);
 #pragma unroll
     for (int i = 0; i < 6; ++i) r.F[i] = D[i] - h * f[i];
