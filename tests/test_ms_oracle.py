@@ -1,0 +1,175 @@
+"""Pins of the oracle's Moulinec-Suquet driver (CPU)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import ms as oms
+from paper_2006_04391_amd import inputs
+from tests import _tensor as T
+
+ELASTIC = lambda E, nu: dict(kind=0, E=E, nu=nu, H=0.0, sigma_y=0.0, sigma0=1.0, eps0=0.0, n=1.0)
+
+
+def _voigt_from_sym(t):
+    return np.array([t[0, 0], t[1, 1], t[2, 2], 2 * t[1, 2], 2 * t[0, 2], 2 * t[0, 1]])
+
+
+def test_green_operator_projects_compatible_strains_and_kills_equilibrated_stress():
+    """Gamma0 : C0 : sym(xi (x) u) = sym(xi (x) u) (compatible fields are
+    reproduced) and Gamma0 : s = 0 for s . xi = 0 (equilibrated fields)."""
+    rng = np.random.default_rng(0)
+    shape = (4, 5, 6)
+    lam0, mu0 = 700.0, 350.0
+    nz, ny, nx = shape
+    for _ in range(10):
+        # away from the Nyquist planes, where +xi and its alias -xi differ per component
+        kz, ky, kx = rng.integers(-1, 2), rng.integers(-2, 3), rng.integers(1, 3)
+        xi = np.array([kx / nx, ky / ny, kz / nz])
+        u = rng.normal(size=3) + 1j * rng.normal(size=3)
+        e = 0.5 * (np.outer(xi, u) + np.outer(u, xi))
+        s = lam0 * np.trace(e) * np.eye(3) + 2 * mu0 * e        # C0 : e
+        tau = np.zeros((6, nz, ny, nx // 2 + 1), dtype=complex)
+        tau[:, kz % nz, ky % ny, kx] = [s[0, 0], s[1, 1], s[2, 2], s[1, 2], s[0, 2], s[0, 1]]
+        out = oms.gamma_apply(tau, shape, lam0, mu0)[:, kz % nz, ky % ny, kx]
+        np.testing.assert_allclose(-out, _voigt_from_sym(e), rtol=1e-12, atol=1e-14)
+        # an equilibrated stress: s . xi = 0
+        w = np.cross(xi, rng.normal(size=3))
+        z = np.cross(xi, w)
+        sq = np.outer(w, w) + np.outer(z, z) * 0.3
+        tau[:, kz % nz, ky % ny, kx] = [sq[0, 0], sq[1, 1], sq[2, 2], sq[1, 2], sq[0, 2], sq[0, 1]]
+        out = oms.gamma_apply(tau, shape, lam0, mu0)[:, kz % nz, ky % ny, kx]
+        assert np.abs(out).max() <= 1e-14 * np.abs(sq).max() / mu0
+
+
+def test_homogeneous_cell_one_iteration():
+    N = 8
+    ph = [ELASTIC(2500.0, 0.35)]
+    E = np.array([1e-3, -2e-4, 0, 0, 5e-4, 0])
+    r = oms.ms_step(np.zeros((6, N ** 3)), np.zeros((6, N ** 3)), np.zeros(N ** 3, np.uint8), ph,
+                    (N, N, N), E, np.zeros(6), 0.1, lam0=500.0, mu0=300.0, tol=1e-12)
+    assert r["iters"] == 1
+    np.testing.assert_allclose(r["eps"], np.repeat(E[:, None], N ** 3, 1), atol=1e-15)
+    sig = T.stress_voigt(T.hooke(2500.0, 0.35, T.strain_tensor(E)))
+    np.testing.assert_allclose(r["sigma_mean"], sig, rtol=1e-12, atol=1e-12)
+
+
+def laminate_sigma(phases_x, fr, E):
+    """Exact mean stress of an elastic laminate with layers normal to x.
+    Tangential strains (yy, zz, yz) are uniform, tractions (xx, xy, xz) are
+    uniform; the remaining strain components average to E."""
+    lam = np.array([T.lame(p["E"], p["nu"])[0] for p in phases_x])
+    mu = np.array([T.lame(p["E"], p["nu"])[1] for p in phases_x])
+    fr = np.asarray(fr)
+    M = lam + 2 * mu
+    Exx, Eyy, Ezz, Eyz, Exz, Exy = E
+    sxx = (Exx + np.sum(fr * lam / M) * (Eyy + Ezz)) / np.sum(fr / M)
+    exx = (sxx - lam * (Eyy + Ezz)) / M
+    sxy = Exy / np.sum(fr / mu)
+    sxz = Exz / np.sum(fr / mu)
+    syy = np.sum(fr * (lam * (exx + Ezz) + M * Eyy))
+    szz = np.sum(fr * (lam * (exx + Eyy) + M * Ezz))
+    syz = np.sum(fr * mu) * Eyz
+    return np.array([sxx, syy, szz, syz, sxz, sxy])
+
+
+def test_laminate_exact():
+    """A voxel laminate (phase varying along x only) reproduces the exact
+    laminate mean stress."""
+    nz, ny, nx = 4, 4, 16
+    ph = [ELASTIC(2500.0, 0.35), ELASTIC(72000.0, 0.22)]
+    layer = (np.arange(nx) >= 11).astype(np.uint8)           # 5 of 16 layers stiff
+    phase = np.broadcast_to(layer[None, None, :], (nz, ny, nx)).reshape(-1).copy()
+    E = np.array([1e-3, 3e-4, -2e-4, 4e-4, -5e-4, 6e-4])
+    r = oms.ms_step(np.zeros((6, phase.size)), np.zeros((6, phase.size)), phase, ph, (nz, ny, nx),
+                    E, np.zeros(6), 0.1, tol=1e-11, max_iter=5000)
+    ref = laminate_sigma(ph, [11 / 16, 5 / 16], E)
+    np.testing.assert_allclose(r["sigma_mean"], ref, rtol=1e-8, atol=1e-8 * np.abs(ref).max())
+
+
+def test_spheres_within_hashin_shtrikman_bounds():
+    N = 16
+    phase = inputs.sphere_phase(N, seed=5, radius=3.0, vol_frac=0.2)
+    c2 = phase.mean()
+    m, f = ELASTIC(2500.0, 0.35), ELASTIC(72000.0, 0.22)
+    l1, m1 = T.lame(m["E"], m["nu"])
+    l2, m2 = T.lame(f["E"], f["nu"])
+    k1, k2 = l1 + 2 * m1 / 3, l2 + 2 * m2 / 3
+    c1 = 1 - c2
+    k_lo = k1 + c2 / (1 / (k2 - k1) + 3 * c1 / (3 * k1 + 4 * m1))
+    k_hi = k2 + c1 / (1 / (k1 - k2) + 3 * c2 / (3 * k2 + 4 * m2))
+    m_lo = m1 + c2 / (1 / (m2 - m1) + 6 * c1 * (k1 + 2 * m1) / (5 * m1 * (3 * k1 + 4 * m1)))
+    m_hi = m2 + c1 / (1 / (m1 - m2) + 6 * c2 * (k2 + 2 * m2) / (5 * m2 * (3 * k2 + 4 * m2)))
+    z = np.zeros((6, N ** 3))
+    e = 1e-3
+    r = oms.ms_step(z, z, phase, [m, f], (N, N, N), [e, e, e, 0, 0, 0], np.zeros(6), 0.1,
+                    tol=1e-8, max_iter=5000)
+    k_eff = r["sigma_mean"][:3].sum() / (9 * e)
+    assert k_lo <= k_eff <= k_hi, (k_lo, k_eff, k_hi)
+    r = oms.ms_step(z, z, phase, [m, f], (N, N, N), [0, 0, 0, 0, 0, e], np.zeros(6), 0.1,
+                    tol=1e-8, max_iter=5000)
+    m_eff = r["sigma_mean"][5] / e
+    assert m_lo <= m_eff <= m_hi, (m_lo, m_eff, m_hi)
+
+
+def test_viscoplastic_step_commits_state_and_relaxes():
+    """Two steps with a flowing matrix: a_{n+1} is committed, the scheme
+    converges below tol, and the mean stress is below the elastic one."""
+    N = 8
+    phase = inputs.sphere_phase(N, seed=6, radius=2.0, vol_frac=0.2)
+    ph = inputs.paper_phases()
+    z = np.zeros((6, N ** 3))
+    E1 = np.array([5e-3, 0, 0, 0, 0, 0])
+    r1 = oms.ms_step(z, z, phase, ph, (N, N, N), E1, np.zeros(6), 1.0, tol=1e-8)
+    assert r1["residual"] <= 1e-8 and r1["iters"] > 1
+    assert np.abs(r1["a"][:, phase == 0]).max() > 0 and np.all(r1["a"][:, phase == 1] == 0)
+    el = [ph[0] | dict(kind=0), ph[1]]
+    r_el = oms.ms_step(z, z, phase, el, (N, N, N), E1, np.zeros(6), 1.0, tol=1e-8)
+    assert r1["sigma_mean"][0] < r_el["sigma_mean"][0]
+    r2 = oms.ms_step(r1["eps"], r1["a"], phase, ph, (N, N, N), 2 * E1, E1, 1.0, tol=1e-8)
+    assert np.allclose(r2["eps"].mean(axis=1), 2 * E1, atol=1e-14)
+
+
+def _gamma_full(tau_full, shape, lam0, mu0):
+    """The averaged operator on the full (signed) frequency grid, for every
+    frequency: components at +-N/2 are averaged over both signs."""
+    nz, ny, nx = shape
+    F = np.stack(np.broadcast_arrays(np.fft.fftfreq(nx)[None, None, :],
+                                     np.fft.fftfreq(ny)[None, :, None],
+                                     np.fft.fftfreq(nz)[:, None, None]), axis=0)
+    nyq = np.abs(F) == 0.5
+    T = np.empty((3, 3) + tau_full.shape[1:], dtype=complex)
+    for c, (i, j) in enumerate(oms.VOIGT_PAIRS):
+        T[i, j] = tau_full[c]
+        T[j, i] = tau_full[c]
+    acc = np.zeros_like(tau_full)
+    cnt = np.zeros(tau_full.shape[1:])
+    for signs in np.ndindex(2, 2, 2):
+        sgn = np.array([1.0 - 2 * s_ for s_ in signs])
+        use = np.ones(tau_full.shape[1:], dtype=bool)
+        for d in range(3):
+            if sgn[d] < 0:
+                use &= nyq[d]
+        q = np.where(nyq, np.abs(F) * sgn[:, None, None, None], F)
+        nrm = np.sqrt((q ** 2).sum(axis=0))
+        nrm[nrm == 0] = 1.0
+        acc += np.where(use, oms._gamma_unit(T, q / nrm, lam0, mu0), 0.0)
+        cnt += use
+    return acc / cnt
+
+
+@pytest.mark.parametrize("shape", [(6, 8, 10), (5, 7, 9), (4, 6, 6)])
+def test_green_operator_keeps_fields_real(shape):
+    """The half-spectrum update equals the full complex-FFT update and the
+    latter is real: the operator is Hermitian-consistent on even grids
+    (Nyquist planes included)."""
+    rng = np.random.default_rng(1)
+    tau = rng.normal(size=(6,) + shape)
+    lam0, mu0 = 600.0, 400.0
+    half = oms.gamma_apply(np.fft.rfftn(tau, axes=(1, 2, 3)), shape, lam0, mu0)
+    half[:, 0, 0, 0] = 0
+    e_half = np.fft.irfftn(half, s=shape, axes=(1, 2, 3))
+    full = _gamma_full(np.fft.fftn(tau, axes=(1, 2, 3)), shape, lam0, mu0)
+    full[:, 0, 0, 0] = 0
+    e_full = np.fft.ifftn(full, axes=(1, 2, 3))
+    assert np.abs(e_full.imag).max() <= 1e-12 * np.abs(e_full.real).max()
+    np.testing.assert_allclose(e_half, e_full.real, rtol=0, atol=1e-12 * np.abs(e_half).max())
