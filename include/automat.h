@@ -154,6 +154,60 @@ int32_t automat_evaluate_backward(int64_t n, const double *eps_new, const double
                                   double *grad_eps, double *grad_a_old, double *grad_params,
                                   void *stream);
 
+/* ------------------------------------------------------------------------
+ * Moulinec-Suquet basic scheme (FFT-based homogenization around the
+ * material-point evaluation; the paper's Section "Example", paragraph
+ * "Material Law Evaluations": each fixed-point iteration makes one material
+ * sweep without tangent). Periodic grid nx * ny * nz, x fastest (point
+ * i = x + nx (y + ny z)); strain-controlled macroscopic load; isotropic
+ * reference medium C0 = (lambda0, mu0); Green operator
+ * Gamma0(xi) = [d_ki q_h q_j + d_hi q_k q_j + d_kj q_h q_i + d_hj q_k q_i]/(4 mu0)
+ *              - (lambda0 + mu0)/(mu0 (lambda0 + 2 mu0)) q_i q_j q_k q_h,
+ * q = xi/|xi|, at every non-zero frequency; the zero frequency carries E.
+ * ------------------------------------------------------------------------ */
+typedef struct automat_ms automat_ms; /* opaque; owns hipFFT plans and work buffers */
+
+typedef struct automat_ms_options {
+    double tol;              /* stop when ||eps' - eps||_2 / ||E|| <= tol (tensor norms,
+                                voxel-averaged L2); > 0 unless fixed_iter */
+    int32_t max_iter;        /* maximum fixed-point iterations per load step, >= 1 */
+    int32_t fixed_iter;      /* nonzero: run exactly max_iter iterations, no test */
+    double lambda0, mu0;     /* reference medium; <= 0 selects the means of the smallest
+                                and largest Lame constants of the phases */
+    double newton_tol;       /* per-point Newton tolerance, > 0 */
+    int32_t newton_max_iter; /* per-point Newton update limit, >= 1 */
+    int32_t reserved;
+} automat_ms_options;
+
+/* Create a solver for an nx * ny * nz grid (each >= 2). params and opts are
+ * copied. Allocates about 9.4 doubles per voxel of device memory on the
+ * current device. Errors: AUTOMAT_EINVAL, AUTOMAT_ENOMEM. */
+int32_t automat_ms_create(int32_t nx, int32_t ny, int32_t nz, const automat_params *params,
+                          const automat_ms_options *opts, automat_ms **out);
+
+/* One load step to the macroscopic strain E_macro[6] (host, engineering
+ * Voigt) with step length h. eps [6][n] (device, in/out) holds the strain
+ * field of the previous step on entry (zeros before the first step) and is
+ * shifted by E_macro - E_previous as the initial guess; on return it is the
+ * converged field. a [6][n] (device, in/out): a_n on entry, a_{n+1} on
+ * return (committed by a final sweep at the converged strain). sigma_out
+ * [6][n] (device) receives that sweep's stress, or NULL. sigma_mean[6]
+ * (host) its voxel average, or NULL. iters (host): fixed-point iterations
+ * used; residual (host): the last ||eps' - eps||_2 / ||E||. Synchronizes
+ * the stream once per iteration (convergence test) unless fixed_iter. */
+int32_t automat_ms_step(automat_ms *ms, const uint8_t *phase, const double *E_macro, double h,
+                        double *eps, double *a, double *sigma_out, double *sigma_mean,
+                        int32_t *iters, double *residual, void *stream);
+
+/* Set the macroscopic strain the next step starts from (e.g. after loading
+ * a checkpointed strain field). */
+int32_t automat_ms_set_macro(automat_ms *ms, const double *E_previous);
+
+/* The reference medium in use. */
+int32_t automat_ms_reference(const automat_ms *ms, double *lambda0, double *mu0);
+
+int32_t automat_ms_destroy(automat_ms *ms);
+
 /* Human-readable text of a return code. */
 const char *automat_strerror(int32_t code);
 

@@ -32,6 +32,13 @@ class Params(ctypes.Structure):
                 ("phase", Phase * MAX_PHASES)]
 
 
+class MsOptions(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("fixed_iter", ctypes.c_int32), ("lambda0", ctypes.c_double),
+                ("mu0", ctypes.c_double), ("newton_tol", ctypes.c_double),
+                ("newton_max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class AutomatError(RuntimeError):
     def __init__(self, fn: str, code: int, msg: str):
         super().__init__(f"{fn} failed: {msg} ({code})")
@@ -50,6 +57,11 @@ SIGNATURES = {
                                    _vp, _vp, ctypes.c_uint32, _vp]),
     "automat_evaluate_backward": (_i32, [_i64, _vp, _vp, _vp, _vp, _vp, _dbl, _vp, _vp, _vp, _vp,
                                          _vp, _vp]),
+    "automat_ms_create": (_i32, [_i32, _i32, _i32, _vp, _vp, _vp]),
+    "automat_ms_step": (_i32, [_vp, _vp, _vp, _dbl, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "automat_ms_set_macro": (_i32, [_vp, _vp]),
+    "automat_ms_reference": (_i32, [_vp, _vp, _vp]),
+    "automat_ms_destroy": (_i32, [_vp]),
     "automat_strerror": (ctypes.c_char_p, [_i32]),
     "automat_version": (ctypes.c_char_p, []),
 }

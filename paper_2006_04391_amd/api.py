@@ -113,3 +113,76 @@ def evaluate_backward(eps, a_old, a_new, phase, phases, h, grad_sigma=None, grad
 
 def version() -> str:
     return load().automat_version().decode()
+
+
+class MS:
+    """Moulinec-Suquet basic-scheme solver on a periodic grid (the library's
+    automat_ms_* entry points). shape = (nz, ny, nx), x fastest."""
+
+    def __init__(self, shape, phases, *, tol=1e-6, max_iter=1000, fixed_iter=False, lambda0=0.0,
+                 mu0=0.0, newton_tol=1e-12, newton_max_iter=50, device=None):
+        if isinstance(shape, int):
+            shape = (shape, shape, shape)
+        self.shape = tuple(int(s) for s in shape)
+        self.n = self.shape[0] * self.shape[1] * self.shape[2]
+        self.phases = list(phases)
+        self.device = torch.device(device) if device is not None else torch.device(
+            "cuda", torch.cuda.current_device())
+        self._params = make_params(self.phases)
+        opts = _lib.MsOptions()
+        opts.tol = float(tol)
+        opts.max_iter = int(max_iter)
+        opts.fixed_iter = 1 if fixed_iter else 0
+        opts.lambda0 = float(lambda0)
+        opts.mu0 = float(mu0)
+        opts.newton_tol = float(newton_tol)
+        opts.newton_max_iter = int(newton_max_iter)
+        self._opts = opts
+        self._h = ctypes.c_void_p()
+        lib = load()
+        nz, ny, nx = self.shape
+        with torch.cuda.device(self.device):
+            rc = lib.automat_ms_create(nx, ny, nz, ctypes.byref(self._params), ctypes.byref(opts),
+                                       ctypes.byref(self._h))
+        check("automat_ms_create", rc)
+
+    def reference(self):
+        lam, mu = ctypes.c_double(), ctypes.c_double()
+        check("automat_ms_reference", load().automat_ms_reference(self._h, ctypes.byref(lam),
+                                                                   ctypes.byref(mu)))
+        return lam.value, mu.value
+
+    def set_macro(self, E_prev):
+        E = (ctypes.c_double * 6)(*[float(x) for x in E_prev])
+        check("automat_ms_set_macro", load().automat_ms_set_macro(self._h, E))
+
+    def step(self, phase, E_macro, h, eps, a, sigma_out=None):
+        """Advance one load step in place (eps, a). Returns (sigma_mean (6,),
+        iterations, last relative strain change)."""
+        dev = self.device
+        eps = _field(eps, "eps", 6, self.n, dev)
+        a = _field(a, "a", 6, self.n, dev)
+        phase = _phase_ids(phase, self.n, dev)
+        if sigma_out is not None:
+            sigma_out = _field(sigma_out, "sigma_out", 6, self.n, dev)
+        E = (ctypes.c_double * 6)(*[float(x) for x in E_macro])
+        mean = (ctypes.c_double * 6)()
+        iters = ctypes.c_int32()
+        res = ctypes.c_double()
+        with torch.cuda.device(dev):
+            rc = load().automat_ms_step(self._h, _ptr(phase), E, float(h), _ptr(eps), _ptr(a),
+                                        _ptr(sigma_out), mean, ctypes.byref(iters),
+                                        ctypes.byref(res), _stream(dev))
+        check("automat_ms_step", rc)
+        return list(mean), iters.value, res.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().automat_ms_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -67,7 +67,7 @@ __device__ __forceinline__ void count_failures(unsigned long long *counter, bool
 __device__ __forceinline__ void lds_reload_point() { asm volatile("" ::: "memory"); }
 
 #ifndef AUTOMAT_EVAL_WAVES
-#define AUTOMAT_EVAL_WAVES 3
+#define AUTOMAT_EVAL_WAVES 2
 #endif
 
 template <bool TANGENT>
@@ -86,6 +86,22 @@ void gsm_eval_kernel(const EvalArgs args) {
     const int64_t n = args.n;
     const double h = args.h;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
+    // Software pipelining over tiles: the inputs of the next tile are loaded
+    // into registers while the current tile computes, so the load latency is
+    // hidden behind the Newton work instead of stalling each tile's start.
+    double nx_e[6], nx_a[6];
+    int nx_p = 0;
+    auto prefetch = [&](int64_t j) {
+        if (j < n) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                nx_e[c] = __builtin_nontemporal_load(args.eps + c * n + j);
+                nx_a[c] = __builtin_nontemporal_load(args.a_old + c * n + j);
+            }
+            nx_p = args.phase[j];
+        }
+    };
+    prefetch((int64_t)blockIdx.x * kBlock + threadIdx.x);
     for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n; base += stride) {
         const int64_t i = base + threadIdx.x;
         if (i >= n) continue;
@@ -93,24 +109,23 @@ void gsm_eval_kernel(const EvalArgs args) {
         bool finite_in = true;
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-            const double e = __builtin_nontemporal_load(args.eps + c * n + i);
-            const double a = __builtin_nontemporal_load(args.a_old + c * n + i);
-            finite_in = finite_in && isfinite(e) && isfinite(a);
-            eps[c * kBlock] = e;
-            an[c * kBlock] = a;
+            finite_in = finite_in && isfinite(nx_e[c]) && isfinite(nx_a[c]);
+            eps[c * kBlock] = nx_e[c];
+            an[c * kBlock] = nx_a[c];
         }
-        const int pid = args.phase[i];
+        const int pid = nx_p;
+        prefetch(i + stride);
         const bool valid = pid < args.n_phases && finite_in;
         const PC &pc = tab[valid ? pid : 0];
         const Model::Phase &prm = pc.prm;
         const bool newton = valid && Model::flows(prm);
 
         double D[6] = {0, 0, 0, 0, 0, 0};
-        Resid cur;
+        Resid2 cur;
         double phi = 0.0;
         int status = valid ? 0 : -1;
         if (newton) {
-            residual<Model>(prm, Strided<kBlock>{eps}, Strided<kBlock>{an}, D, h, cur);
+            residual2<Model>(prm, pc.Kinv, Strided<kBlock>{eps}, Strided<kBlock>{an}, D, h, cur);
             phi = h * cur.psi;
         }
         bool done = !newton;
@@ -139,19 +154,12 @@ void gsm_eval_kernel(const EvalArgs args) {
             }
             if (__ballot(!done) == 0) break;
             if (!done) {
-                // Newton matrix M = K^-1 + h Psi'' and its Cholesky factor
-                double y[6], delta[6];
-                bool spd;
-                {
-                    double M[21], idg[6];
-                    Model::psi_hess(prm, cur.A, M);
+                // Cholesky factor of M = K^-1 + h Psi'' (from the last residual)
+                double y[6], delta[6], idg[6];
+                const bool spd = la::cholesky6(cur.M, idg);
 #pragma unroll
-                    for (int c = 0; c < 21; ++c) M[c] = pc.Kinv[c] + h * M[c];
-                    spd = la::cholesky6(M, idg);
-#pragma unroll
-                    for (int c = 0; c < 6; ++c) y[c] = cur.F[c];
-                    la::chol_solve6(M, idg, y);
-                }
+                for (int c = 0; c < 6; ++c) y[c] = cur.F[c];
+                la::chol_solve6(cur.M, idg, y);
                 lds_reload_point();
                 if (!spd) {
                     done = true;
@@ -168,7 +176,8 @@ void gsm_eval_kernel(const EvalArgs args) {
                     for (int c = 0; c < 6; ++c) D[c] -= delta[c];
                     for (;;) {
                         lds_reload_point();
-                        residual<Model>(prm, Strided<kBlock>{eps}, Strided<kBlock>{an}, D, h, cur);
+                        residual2<Model>(prm, pc.Kinv, Strided<kBlock>{eps}, Strided<kBlock>{an}, D,
+                                         h, cur);
                         dphi = -t * s1 + 0.5 * t * t * s2 + h * (cur.psi - psi0);
                         if (dphi <= -1e-4 * t * slope + 1e-13 * phi || t < 0x1p-30) break;
                         t *= 0.5;
@@ -204,10 +213,8 @@ void gsm_eval_kernel(const EvalArgs args) {
         if constexpr (TANGENT) {
             double C[21];
             if (newton) {
-                double M[21], idg[6];
-                Model::psi_hess(prm, cur.A, M);
-#pragma unroll
-                for (int c = 0; c < 21; ++c) M[c] = pc.Kinv[c] + h * M[c];
+                // M at the converged point came with the last residual
+                double *M = cur.M, idg[6];
                 la::cholesky6(M, idg);
                 double W[6][6];
 #pragma unroll

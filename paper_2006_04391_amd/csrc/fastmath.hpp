@@ -39,8 +39,11 @@ namespace fm {
 // table rather than in the instruction stream: the compiler then loads them
 // (uniform scalar loads) where they are used instead of materializing all of
 // them once per kernel and holding them in ~50 vector registers.
+#ifndef AUTOMAT_FM_TABLE_SPACE
+#define AUTOMAT_FM_TABLE_SPACE __device__
+#endif
 #if defined(__HIP_DEVICE_COMPILE__)
-#define AUTOMAT_FM_TABLE static __device__
+#define AUTOMAT_FM_TABLE static AUTOMAT_FM_TABLE_SPACE
 #else
 #define AUTOMAT_FM_TABLE static
 #endif

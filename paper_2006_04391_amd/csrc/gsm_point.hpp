@@ -130,6 +130,32 @@ AD_FN void residual(const typename Model::Phase &prm, const V &eps, const V &an,
     for (int i = 0; i < 6; ++i) r.F[i] = D[i] - h * f[i];
 }
 
+// Residual together with the Newton matrix of the same point,
+// M = K^{-1} + h Psi''(A), from one forward-over-reverse sweep of Psi: the
+// next Newton step (or the tangent, at the converged point) factors this M,
+// so the transcendental part of Psi is evaluated once per trial point.
+struct Resid2 : Resid {
+    double M[21];
+};
+
+template <class Model, class V>
+AD_FN void residual2(const typename Model::Phase &prm, const double *Kinv, const V &eps,
+                     const V &an, const double *D, double h, Resid2 &r) {
+    double a[6], e[6], f[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        a[i] = an[i] + D[i];
+        e[i] = eps[i];
+    }
+    Model::gen_stress(prm, e, a, r.A);
+    asm volatile("" ::: "memory");  // re-read the phase constants for the Psi sweep
+    r.psi = Model::psi_grad_hess(prm, r.A, f, r.M);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) r.F[i] = D[i] - h * f[i];
+#pragma unroll
+    for (int i = 0; i < 21; ++i) r.M[i] = Kinv[i] + h * r.M[i];
+}
+
 // Stress-criterion test: ||d sigma / d a . F||_inf <= tol ||sigma||_inf at
 // a = a_n + D, with both terms from the AD layer.
 template <class Model, class V>

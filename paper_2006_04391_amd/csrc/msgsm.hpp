@@ -165,6 +165,15 @@ struct MSGSM {
         return val;
     }
 
+    // Psi(A), f = dPsi/dA and Psi''(A) (packed lower triangle) by one sweep
+    AD_FN static double psi_grad_hess(const Phase &p, const double *A, double *f, double *Hp) {
+        Leaves6<PS_A> la(A);
+        double val = 0.0;
+        with_psi(la, p.sy, p.coef, p.is0, p.pq, p.sy == 0.0,
+                 [&](const auto &e) { val = ad::value_grad_hess6<PS_A>(e, f, Hp); });
+        return val;
+    }
+
     // Psi''(A), packed lower triangle, by one sweep
     AD_FN static void psi_hess(const Phase &p, const double *A, double *Hp) {
         Leaves6<PS_A> la(A);

@@ -1,0 +1,115 @@
+"""Moulinec-Suquet driver on the GPU vs the oracle's driver (CPU)."""
+import numpy as np
+import pytest
+
+from oracle import ms as oms
+from paper_2006_04391_amd import inputs
+from tests import _tensor as T
+from tests.test_ms_oracle import ELASTIC, laminate_sigma
+from tests.test_parity_gpu import N, T as TT
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_run(shape, phase, phases, loads, h, **opts):
+    from paper_2006_04391_amd import api
+    n = shape[0] * shape[1] * shape[2]
+    ms = api.MS(shape, phases, **opts)
+    eps = torch.zeros((6, n), dtype=torch.float64, device="cuda")
+    a = torch.zeros_like(eps)
+    sig = torch.empty_like(eps)
+    ph = TT(phase)
+    out = []
+    for E in loads:
+        mean, it, res = ms.step(ph, E, h, eps, a, sigma_out=sig)
+        torch.cuda.synchronize()
+        out.append(dict(eps=N(eps), a=N(a), sigma=N(sig), sigma_mean=np.array(mean), iters=it,
+                        residual=res))
+    ms.close()
+    return out
+
+
+def _oracle_run(shape, phase, phases, loads, h, **opts):
+    n = shape[0] * shape[1] * shape[2]
+    eps = np.zeros((6, n))
+    a = np.zeros((6, n))
+    prev = np.zeros(6)
+    out = []
+    for E in loads:
+        r = oms.ms_step(eps, a, phase, phases, shape, E, prev, h, **opts)
+        eps, a, prev = r["eps"], r["a"], np.asarray(E, dtype=float)
+        out.append(r)
+    return out
+
+
+def _rel(x, y):
+    return np.linalg.norm(x - y) / max(np.linalg.norm(y), 1e-300)
+
+
+def test_homogeneous_cell():
+    shape = (6, 6, 6)
+    E = [1e-3, -2e-4, 0, 0, 5e-4, 0]
+    r = _gpu_run(shape, np.zeros(216, np.uint8), [ELASTIC(2500.0, 0.35)], [E], 0.1,
+                 lambda0=500.0, mu0=300.0, tol=1e-12)[0]
+    assert r["iters"] == 1
+    np.testing.assert_allclose(r["eps"], np.repeat(np.array(E)[:, None], 216, 1), atol=1e-15)
+    sig = T.stress_voigt(T.hooke(2500.0, 0.35, T.strain_tensor(np.array(E))))
+    np.testing.assert_allclose(r["sigma_mean"], sig, rtol=1e-12, atol=1e-12)
+
+
+def test_laminate_exact():
+    nz, ny, nx = 4, 4, 16
+    ph = [ELASTIC(2500.0, 0.35), ELASTIC(72000.0, 0.22)]
+    layer = (np.arange(nx) >= 11).astype(np.uint8)
+    phase = np.broadcast_to(layer[None, None, :], (nz, ny, nx)).reshape(-1).copy()
+    E = [1e-3, 3e-4, -2e-4, 4e-4, -5e-4, 6e-4]
+    r = _gpu_run((nz, ny, nx), phase, ph, [E], 0.1, tol=1e-11, max_iter=5000)[0]
+    ref = laminate_sigma(ph, [11 / 16, 5 / 16], np.array(E))
+    np.testing.assert_allclose(r["sigma_mean"], ref, rtol=1e-8, atol=1e-8 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("shape", [(12, 12, 12), (6, 10, 12)])
+def test_lockstep_parity_viscoplastic(shape):
+    """Fixed iteration counts on both sides: fields agree to rounding."""
+    nz, ny, nx = shape
+    rng = np.random.default_rng(7)
+    phase = (rng.random(nz * ny * nx) < 0.2).astype(np.uint8)
+    ph = inputs.paper_phases()
+    loads = [[2e-3 * k, -5e-4 * k, 0, 0, 3e-4 * k, 0] for k in (1, 2, 3)]
+    kw = dict(max_iter=12, fixed_iter=True)
+    g = _gpu_run(shape, phase, ph, loads, 1.0, **kw)
+    o = _oracle_run(shape, phase, ph, loads, 1.0, tol=0.0, **kw)
+    for gs, os_ in zip(g, o):
+        assert gs["iters"] == os_["iters"] == 12
+        for key in ("eps", "a", "sigma"):
+            assert _rel(gs[key], os_[key]) <= 1e-10, key
+        np.testing.assert_allclose(gs["sigma_mean"], os_["sigma_mean"], rtol=1e-10,
+                                   atol=1e-10 * np.abs(os_["sigma_mean"]).max())
+        assert abs(gs["residual"] - os_["residual"]) <= 1e-8 * os_["residual"]
+    assert np.abs(g[-1]["a"]).max() > 0
+
+
+def test_free_running_matches_oracle_within_tolerance():
+    N_ = 12
+    phase = inputs.sphere_phase(N_, seed=8, radius=2.5, vol_frac=0.2)
+    ph = inputs.config_phases()
+    loads = [[1e-3 * 0.1 * k, 0, 0, 0, 0, 0] for k in (1, 2, 3)]
+    tol = 1e-6
+    g = _gpu_run((N_,) * 3, phase, ph, loads, 0.1, tol=tol)
+    o = _oracle_run((N_,) * 3, phase, ph, loads, 0.1, tol=tol)
+    for gs, os_ in zip(g, o):
+        assert abs(gs["iters"] - os_["iters"]) <= 1
+        assert gs["residual"] <= tol
+        np.testing.assert_allclose(gs["sigma_mean"], os_["sigma_mean"], rtol=10 * tol,
+                                   atol=10 * tol * np.abs(os_["sigma_mean"]).max())
+
+
+def test_invalid_arguments():
+    from paper_2006_04391_amd import api, _lib
+    with pytest.raises(_lib.AutomatError):
+        api.MS((1, 4, 4), inputs.config_phases())
+    with pytest.raises(_lib.AutomatError):
+        api.MS((4, 4, 4), inputs.config_phases(), tol=0.0)
+    with pytest.raises(_lib.AutomatError):
+        api.MS((4, 4, 4), inputs.config_phases(), max_iter=0)
