@@ -38,7 +38,7 @@ BYTES_PER_POINT_TANGENT = BYTES_PER_POINT + 36 * 8            # 481
 # traffic null until it is measured again.
 MEASURED_TRAFFIC = {"03d7b0dd077789af": 3.246e9}
 KERNEL_SOURCES = ["automat.hip", "ad.hpp", "fastmath.hpp", "linalg6.hpp", "msgsm.hpp",
-                  "gsm_point.hpp"]
+                  "gsm_point.hpp", "gsm_kernel.hpp"]
 
 
 def kernel_source_hash():
@@ -108,6 +108,10 @@ def main():
     ap.add_argument("--side", type=int, default=256, help="cube side (256 = the headline batch)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-tangent", action="store_true", help="skip the tangent variant")
+    ap.add_argument("--serve-requests", type=int, default=1000,
+                    help="requests in the serving stream (0 skips the serving leg)")
+    ap.add_argument("--serve-workers", type=int, default=8,
+                    help="host processes generating the requests' microstructures")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (known traffic: 1 GiB read, "
                          "1 GiB written) so profiler byte counters can be scaled")
@@ -117,6 +121,18 @@ def main():
                                    "(the per-point path shards by contiguous point ranges, "
                                    "see the design notes)"}))
         sys.exit(2)
+
+    # the serving stream's microstructures are generated in worker processes
+    # before the GPU is initialised
+    serve_reqs = serve_fields = None
+    if args.serve_requests > 0:
+        from paper_2006_04391_amd import inputs, serve
+        t0 = time.perf_counter()
+        serve_reqs = inputs.serving_requests(count=args.serve_requests, rate=200.0, seed=4)
+        serve_fields = serve.prepare_fields(serve_reqs, workers=args.serve_workers)
+        log(f"[bench] serving stream: {len(serve_reqs)} requests, "
+            f"{sum(q.n for q in serve_reqs):.3e} voxels, generated in "
+            f"{time.perf_counter() - t0:.1f} s")
 
     import torch
     from paper_2006_04391_amd import api, inputs
@@ -185,17 +201,33 @@ def main():
     }
 
     if not args.no_tangent:
-        tan = torch.empty((36, n), dtype=torch.float64, device=dev)
-
         def step_t():
             api.evaluate(eps, a_old, phase, ps.phases, ps.h, ps.tol, ps.max_iter,
                          sigma_out=sigma, a_out=a_new, tangent=True)
-        del tan
         tt, each_t, _ = time_calls(step_t, max(3, args.steps // 4), 1, stream)
         ms_t = tt / max(3, args.steps // 4)
         out["tangent"] = {"ms_per_step": ms_t, "value": n / (ms_t * 1e-3), "unit": "updates/s",
                           "hbm_gbs": BYTES_PER_POINT_TANGENT * n / (ms_t * 1e-3) / 1e9}
         log(f"[bench] tangent: {ms_t:.3f} ms/step")
+
+    if serve_reqs is not None:
+        from paper_2006_04391_amd import serve
+        del eps, a_old, phase, sigma, a_new
+        torch.cuda.empty_cache()
+        sv = {"workload": f"{len(serve_reqs)} requests, Poisson arrivals 200/s, cube side "
+                          "log-uniform in [32, 256], fibre or sphere microstructure, phase "
+                          "parameters jittered +-10 %, 1-10 load steps each, HBM budget 200 GB"}
+        for saturate in (False, True):
+            for sequential in (False, True):
+                r = serve.replay(serve_reqs, serve_fields, sequential=sequential,
+                                 saturate=saturate)
+                key = ("saturated_" if saturate else "poisson_") + r["mode"]
+                sv[key] = r
+                log(f"[bench] serving {key}: {r['throughput']:.3e} updates/s, "
+                    f"p50 {r['latency_p50_s'] * 1e3:.1f} ms, p99 {r['latency_p99_s'] * 1e3:.1f} ms, "
+                    f"{r['launches']} launches, makespan {r['makespan_s']:.2f} s")
+        out["serving"] = sv
+        del serve_fields
 
     if not args.no_cpu:
         log("[bench] timing the CPU oracle ...")

@@ -208,6 +208,80 @@ int32_t automat_ms_reference(const automat_ms *ms, double *lambda0, double *mu0)
 
 int32_t automat_ms_destroy(automat_ms *ms);
 
+/* ------------------------------------------------------------------------
+ * Continuous-batching service (the paper's chunked evaluation with streams
+ * that overlap transfers and computation, section "Computational Layout,
+ * Profiling and Performance Limiters", recast for device-resident state).
+ * Requests of uneven sizes, each with several load steps and its own phase
+ * table, are admitted in arrival order while their device block (97 bytes
+ * per point plus the phase tables) fits in the server's arena, one device
+ * allocation of the whole budget made at creation. Every round launches one
+ * kernel over the next load step of every admitted request; requests that
+ * arrive meanwhile are uploaded on a second stream while that kernel runs
+ * and join the next round. Internal variables stay on the device between
+ * steps. The strain of step j of K at point i is (j / K) E_final +
+ * noise_std z, z standard normal from Philox4x32-10 (Salmon et al. 2011)
+ * keyed by seed with counter (i, j, w) and the Box-Muller transform.
+ * Results do not depend on the rest of the batch.
+ * ------------------------------------------------------------------------ */
+typedef struct automat_server automat_server; /* opaque; owns a scheduler thread, two streams
+                                                 and the arena */
+
+typedef struct automat_request {
+    int64_t n;             /* points, >= 1 */
+    const uint8_t *phase;  /* host [n] phase ids; must stay valid until the result arrives */
+    automat_params params; /* phase table of this request */
+    double h;              /* step length, > 0 */
+    double tol;            /* Newton tolerance, > 0 */
+    int32_t max_iter;      /* Newton update limit, >= 1 */
+    int32_t steps;         /* load steps K, >= 1 */
+    double E_final[6];     /* macro strain at step K (engineering Voigt) */
+    double noise_std;      /* standard deviation of the per-point strain noise, >= 0 */
+    uint64_t seed;         /* generator key */
+    const double *a_init;  /* host [6][n] initial internal variables, or NULL for zero */
+    double *sigma_host;    /* host [6][n] stress after the last step, or NULL */
+    double *a_host;        /* host [6][n] internal variables after the last step, or NULL */
+    double t_arrival;      /* arrival time on the server clock (latency origin); < 0: at submit */
+} automat_request;
+
+typedef struct automat_result {
+    uint64_t id;
+    int32_t status;        /* AUTOMAT_OK, AUTOMAT_ENOMEM, AUTOMAT_EHIP; AUTOMAT_EINVAL if cancelled */
+    int32_t steps_done;
+    int64_t n;
+    int64_t nonconverged;  /* point-steps that did not converge */
+    double t_arrival, t_admit, t_done; /* server clock, seconds */
+} automat_result;
+
+typedef struct automat_server_stats_t {
+    double clock_s;        /* server clock now */
+    int64_t pending, active, used_bytes, launches, updates;
+    double busy_s;         /* time spent in batch launches */
+} automat_server_stats_t;
+
+/* Start a server on the current device. hbm_budget_bytes (>= 4096) is
+ * allocated at once as the arena that holds every admitted request;
+ * max_batch_points (0 = unbounded) bounds the points of one launch (at least
+ * one request is always taken); sequential != 0 admits one request at a
+ * time (the per-request baseline). Errors: AUTOMAT_EINVAL, AUTOMAT_ENOMEM
+ * (the budget cannot be allocated), AUTOMAT_EHIP. */
+int32_t automat_server_create(size_t hbm_budget_bytes, int64_t max_batch_points,
+                              int32_t sequential, automat_server **out);
+
+/* Queue a request (copied; the host arrays it points to must stay valid until
+ * its result is polled). Errors: AUTOMAT_EINVAL, AUTOMAT_EBUDGET (larger than
+ * the whole budget). */
+int32_t automat_server_submit(automat_server *server, const automat_request *req, uint64_t *id);
+
+/* Move up to max finished results to out; *count receives their number. */
+int32_t automat_server_poll(automat_server *server, automat_result *out, int32_t max,
+                            int32_t *count);
+
+int32_t automat_server_stats(automat_server *server, automat_server_stats_t *stats);
+
+/* Finish the admitted requests, cancel the queued ones, stop the scheduler. */
+int32_t automat_server_destroy(automat_server *server);
+
 /* Human-readable text of a return code. */
 const char *automat_strerror(int32_t code);
 

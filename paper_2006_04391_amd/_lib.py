@@ -39,6 +39,30 @@ class MsOptions(ctypes.Structure):
                 ("newton_max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("phase", ctypes.POINTER(ctypes.c_uint8)),
+                ("params", Params), ("h", ctypes.c_double), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("steps", ctypes.c_int32),
+                ("E_final", ctypes.c_double * 6), ("noise_std", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("a_init", ctypes.POINTER(ctypes.c_double)),
+                ("sigma_host", ctypes.POINTER(ctypes.c_double)),
+                ("a_host", ctypes.POINTER(ctypes.c_double)), ("t_arrival", ctypes.c_double)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("steps_done", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("nonconverged", ctypes.c_int64), ("t_arrival", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("clock_s", ctypes.c_double), ("pending", ctypes.c_int64),
+                ("active", ctypes.c_int64), ("used_bytes", ctypes.c_int64),
+                ("launches", ctypes.c_int64), ("updates", ctypes.c_int64),
+                ("busy_s", ctypes.c_double)]
+
+
 class AutomatError(RuntimeError):
     def __init__(self, fn: str, code: int, msg: str):
         super().__init__(f"{fn} failed: {msg} ({code})")
@@ -62,6 +86,11 @@ SIGNATURES = {
     "automat_ms_set_macro": (_i32, [_vp, _vp]),
     "automat_ms_reference": (_i32, [_vp, _vp, _vp]),
     "automat_ms_destroy": (_i32, [_vp]),
+    "automat_server_create": (_i32, [ctypes.c_size_t, _i64, _i32, _vp]),
+    "automat_server_submit": (_i32, [_vp, _vp, _vp]),
+    "automat_server_poll": (_i32, [_vp, _vp, _i32, _vp]),
+    "automat_server_stats": (_i32, [_vp, _vp]),
+    "automat_server_destroy": (_i32, [_vp]),
     "automat_strerror": (ctypes.c_char_p, [_i32]),
     "automat_version": (ctypes.c_char_p, []),
 }

@@ -186,3 +186,137 @@ class MS:
             self.close()
         except Exception:
             pass
+
+
+def _phases_from_tensor(params, kinds):
+    vals = params.detach().to("cpu", torch.float64).tolist()
+    return [dict(kind=int(k), E=v[0], nu=v[1], H=v[2], sigma_y=v[3], sigma0=v[4], eps0=v[5], n=v[6])
+            for k, v in zip(kinds, vals)]
+
+
+class AutoMatFn(torch.autograd.Function):
+    """Differentiable implicit-Euler evaluation.
+
+    forward(eps (6, n), a_old (6, n), params (n_phases, 7), phase (n,), kinds,
+            h, tol, max_iter) -> (sigma (6, n), a_new (6, n))
+
+    params rows are (E, nu, H, sigma_y, sigma0, eps0, n) per phase and may
+    require grad; kinds is a sequence of phase kinds (0 elastic, 1
+    viscoplastic). The backward is the library's vector-Jacobian product
+    (implicit function theorem through the converged Newton system; the step
+    length carries no derivative)."""
+
+    @staticmethod
+    def forward(ctx, eps, a_old, params, phase, kinds, h=0.1, tol=1e-12, max_iter=50):
+        phases = _phases_from_tensor(params, kinds)
+        sigma, a_new = evaluate(eps.detach(), a_old.detach(), phase, phases, h, tol, max_iter)
+        ctx.save_for_backward(eps, a_old, a_new, phase)
+        ctx.phases = phases
+        ctx.h = h
+        ctx.params_device = params.device
+        return sigma, a_new
+
+    @staticmethod
+    def backward(ctx, g_sigma, g_a):
+        eps, a_old, a_new, phase = ctx.saved_tensors
+        gs = g_sigma.contiguous() if g_sigma is not None else None
+        ga = g_a.contiguous() if g_a is not None else None
+        geps, gan, gpar = evaluate_backward(eps.detach(), a_old.detach(), a_new, phase, ctx.phases,
+                                            ctx.h, gs, ga,
+                                            want_a_old=ctx.needs_input_grad[1],
+                                            want_params=ctx.needs_input_grad[2])
+        if gpar is not None:
+            gpar = gpar.to(ctx.params_device)
+        return geps, gan, gpar, None, None, None, None, None
+
+
+def automat(eps, a_old, params, phase, kinds, h=0.1, tol=1e-12, max_iter=50):
+    """Functional form of AutoMatFn.apply."""
+    return AutoMatFn.apply(eps, a_old, params, phase, tuple(kinds), h, tol, max_iter)
+
+
+class Server:
+    """Continuous-batching evaluation service (the library's
+    automat_server_* entry points). submit() queues a request whose host
+    arrays stay referenced here until its result is polled."""
+
+    def __init__(self, budget_bytes, max_batch_points=0, sequential=False, device=None):
+        self.device = torch.device(device) if device is not None else torch.device(
+            "cuda", torch.cuda.current_device())
+        self._h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = load().automat_server_create(ctypes.c_size_t(int(budget_bytes)),
+                                              int(max_batch_points), 1 if sequential else 0,
+                                              ctypes.byref(self._h))
+        check("automat_server_create", rc)
+        self._keep = {}
+
+    def clock(self):
+        return self.stats()["clock_s"]
+
+    def submit(self, phase, phases, steps, E_final, noise_std, seed, h=0.1, tol=1e-12,
+               max_iter=50, a_init=None, want_fields=False, arrival=-1.0):
+        """phase: numpy uint8 (n,). Returns the request id; with want_fields
+        the final sigma and a (6, n) arrive in the polled result."""
+        import numpy as np
+        phase = np.ascontiguousarray(phase, dtype=np.uint8)
+        n = phase.shape[0]
+        req = _lib.Request()
+        req.n = n
+        req.phase = phase.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        req.params = make_params(phases)
+        req.h, req.tol, req.max_iter, req.steps = float(h), float(tol), int(max_iter), int(steps)
+        for c in range(6):
+            req.E_final[c] = float(E_final[c])
+        req.noise_std = float(noise_std)
+        req.seed = int(seed) & ((1 << 64) - 1)
+        keep = [phase]
+        if a_init is not None:
+            a_init = np.ascontiguousarray(a_init, dtype=np.float64)
+            req.a_init = a_init.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            keep.append(a_init)
+        sig = a = None
+        if want_fields:
+            sig = np.empty((6, n))
+            a = np.empty((6, n))
+            req.sigma_host = sig.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            req.a_host = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        req.t_arrival = float(arrival)
+        rid = ctypes.c_uint64()
+        check("automat_server_submit", load().automat_server_submit(self._h, ctypes.byref(req),
+                                                                     ctypes.byref(rid)))
+        self._keep[rid.value] = (keep, sig, a)
+        return rid.value
+
+    def poll(self, max_results=1024):
+        buf = (_lib.Result * max_results)()
+        cnt = ctypes.c_int32()
+        check("automat_server_poll", load().automat_server_poll(self._h, buf, max_results,
+                                                                 ctypes.byref(cnt)))
+        out = []
+        for k in range(cnt.value):
+            r = buf[k]
+            d = dict(id=r.id, status=r.status, steps_done=r.steps_done, n=r.n,
+                     nonconverged=r.nonconverged, t_arrival=r.t_arrival, t_admit=r.t_admit,
+                     t_done=r.t_done)
+            _, sig, a = self._keep.pop(r.id, (None, None, None))
+            if sig is not None:
+                d["sigma"], d["a"] = sig, a
+            out.append(d)
+        return out
+
+    def stats(self):
+        st = _lib.ServerStats()
+        check("automat_server_stats", load().automat_server_stats(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in st._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().automat_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -17,15 +17,13 @@
 #include <mutex>
 
 #include "automat.h"
-#include "gsm_point.hpp"
+#include "gsm_kernel.hpp"
 #include "host_common.hpp"
 
 namespace automat {
 
 using Model = MSGSM;
 using PC = PhaseConst<Model>;
-
-constexpr int kBlock = 256;
 
 struct EvalArgs {
     int64_t n;
@@ -44,27 +42,6 @@ struct EvalArgs {
     int32_t reserved;
     Model::Phase phases[AUTOMAT_MAX_PHASES];
 };
-
-__device__ __forceinline__ bool finite6(const double *x) {
-    bool ok = true;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) ok = ok && isfinite(x[i]);
-    return ok;
-}
-
-// Count lanes with a non-converged or invalid point, one atomic per wave.
-__device__ __forceinline__ void count_failures(unsigned long long *counter, bool failed) {
-    const unsigned long long mask = __ballot(failed);
-    if (counter && mask) {
-        const int leader = __ffsll((long long)mask) - 1;
-        if ((int)(threadIdx.x & 63) == leader) atomicAdd(counter, (unsigned long long)__popcll(mask));
-    }
-}
-
-// Keeps the compiler from hoisting LDS reads (per-phase constants, the
-// staged inputs) out of the Newton loop into registers: they are cheap to
-// re-read, and holding them would cost ~90 VGPRs and most of the occupancy.
-__device__ __forceinline__ void lds_reload_point() { asm volatile("" ::: "memory"); }
 
 #ifndef AUTOMAT_EVAL_WAVES
 #define AUTOMAT_EVAL_WAVES 2
@@ -117,93 +94,9 @@ void gsm_eval_kernel(const EvalArgs args) {
         prefetch(i + stride);
         const bool valid = pid < args.n_phases && finite_in;
         const PC &pc = tab[valid ? pid : 0];
-        const Model::Phase &prm = pc.prm;
-        const bool newton = valid && Model::flows(prm);
-
-        double D[6] = {0, 0, 0, 0, 0, 0};
-        Resid2 cur;
-        double phi = 0.0;
-        int status = valid ? 0 : -1;
-        if (newton) {
-            residual2<Model>(prm, pc.Kinv, Strided<kBlock>{eps}, Strided<kBlock>{an}, D, h, cur);
-            phi = h * cur.psi;
-        }
-        bool done = !newton;
-        int k = 0;
-        for (;;) {
-            lds_reload_point();
-            if (!done) {
-                bool zero = true;
-#pragma unroll
-                for (int c = 0; c < 6; ++c) zero = zero && (cur.F[c] == 0.0);
-                bool conv = zero;
-                if (!conv && k >= 1) {
-                    if (args.flags & AUTOMAT_SIGMA_CRITERION)
-                        conv = sigma_converged<Model>(prm, Strided<kBlock>{eps}, Strided<kBlock>{an},
-                                                      D, cur.F, args.tol);
-                    else
-                        conv = la::norm_inf6(cur.F) <= args.tol * la::norm_inf6(D);
-                }
-                if (conv) {
-                    done = true;
-                    status = k;
-                } else if (k >= args.max_iter) {
-                    done = true;
-                    status = -1;
-                }
-            }
-            if (__ballot(!done) == 0) break;
-            if (!done) {
-                // Cholesky factor of M = K^-1 + h Psi'' (from the last residual)
-                double y[6], delta[6], idg[6];
-                const bool spd = la::cholesky6(cur.M, idg);
-#pragma unroll
-                for (int c = 0; c < 6; ++c) y[c] = cur.F[c];
-                la::chol_solve6(cur.M, idg, y);
-                lds_reload_point();
-                if (!spd) {
-                    done = true;
-                    status = -1;
-                } else {
-                    la::symv6(pc.Kinv, y, delta);
-                    const double slope = la::dot6(cur.F, y);
-                    const double s1 = la::dot6(D, y), s2 = la::dot6(delta, y);
-                    const double psi0 = cur.psi;
-                    // full step first; a rejected trial D - t delta moves to
-                    // D - t/2 delta = (D - t delta) + t/2 delta in place
-                    double t = 1.0, dphi;
-#pragma unroll
-                    for (int c = 0; c < 6; ++c) D[c] -= delta[c];
-                    for (;;) {
-                        lds_reload_point();
-                        residual2<Model>(prm, pc.Kinv, Strided<kBlock>{eps}, Strided<kBlock>{an}, D,
-                                         h, cur);
-                        dphi = -t * s1 + 0.5 * t * t * s2 + h * (cur.psi - psi0);
-                        if (dphi <= -1e-4 * t * slope + 1e-13 * phi || t < 0x1p-30) break;
-                        t *= 0.5;
-#pragma unroll
-                        for (int c = 0; c < 6; ++c) D[c] += t * delta[c];
-                    }
-                    phi += dphi;
-                    ++k;
-                }
-            }
-        }
-        lds_reload_point();
-
-        // outputs
-        double sig[6], anew[6], epsv[6];
-#pragma unroll
-        for (int c = 0; c < 6; ++c) {
-            anew[c] = newton ? an[c * kBlock] + D[c] : an[c * kBlock];
-            epsv[c] = eps[c * kBlock];
-        }
-        if (valid) {
-            Model::stress(prm, epsv, anew, sig);
-        } else {
-#pragma unroll
-            for (int c = 0; c < 6; ++c) sig[c] = anew[c] = NAN;
-        }
+        double sig[6], anew[6], C[21];
+        const int status = solve_point<Model, TANGENT>(pc, valid, eps, an, h, args.tol, args.max_iter,
+                                                       args.flags, sig, anew, C);
 #pragma unroll
         for (int c = 0; c < 6; ++c) __builtin_nontemporal_store(sig[c], args.sigma + c * n + i);
         if (args.a_out) {
@@ -211,37 +104,6 @@ void gsm_eval_kernel(const EvalArgs args) {
             for (int c = 0; c < 6; ++c) __builtin_nontemporal_store(anew[c], args.a_out + c * n + i);
         }
         if constexpr (TANGENT) {
-            double C[21];
-            if (newton) {
-                // M at the converged point came with the last residual
-                double *M = cur.M, idg[6];
-                la::cholesky6(M, idg);
-                double W[6][6];
-#pragma unroll
-                for (int j = 0; j < 6; ++j) {
-                    double col[6];
-#pragma unroll
-                    for (int r = 0; r < 6; ++r) col[r] = pc.R[r * 6 + j];
-                    la::forward6(M, idg, col);
-#pragma unroll
-                    for (int r = 0; r < 6; ++r) W[r][j] = col[r];
-                }
-#pragma unroll
-                for (int r = 0; r < 6; ++r)
-#pragma unroll
-                    for (int c = 0; c <= r; ++c) {
-                        double s = pc.C0[la::pk(r, c)];
-#pragma unroll
-                        for (int q = 0; q < 6; ++q) s += W[q][r] * W[q][c];
-                        C[la::pk(r, c)] = s;
-                    }
-            } else if (valid) {
-#pragma unroll
-                for (int c = 0; c < 21; ++c) C[c] = pc.Cee[c];
-            } else {
-#pragma unroll
-                for (int c = 0; c < 21; ++c) C[c] = NAN;
-            }
 #pragma unroll
             for (int r = 0; r < 6; ++r)
 #pragma unroll

@@ -1,0 +1,165 @@
+// gsm_kernel.hpp -- the per-point implicit-Euler solve shared by the
+// kernels that evaluate material points (plain fields, serving batches).
+// One lane per point; the point's eps and a_n are staged in LDS (stride
+// kBlock) and the phase constants sit in an LDS table.
+#pragma once
+
+#include "gsm_point.hpp"
+
+namespace automat {
+
+constexpr int kBlock = 256;
+
+// Keeps the compiler from hoisting LDS reads (per-phase constants, the
+// staged inputs) out of the Newton loop into registers: they are cheap to
+// re-read, and holding them would cost ~90 VGPRs and most of the occupancy.
+__device__ __forceinline__ void lds_reload_point() { asm volatile("" ::: "memory"); }
+
+__device__ __forceinline__ bool finite6(const double *x) {
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) ok = ok && isfinite(x[i]);
+    return ok;
+}
+
+// Count lanes with a non-converged or invalid point, one atomic per wave.
+__device__ __forceinline__ void count_failures(unsigned long long *counter, bool failed) {
+    const unsigned long long mask = __ballot(failed);
+    if (counter && mask) {
+        const int leader = __ffsll((long long)mask) - 1;
+        if ((int)(threadIdx.x & 63) == leader) atomicAdd(counter, (unsigned long long)__popcll(mask));
+    }
+}
+
+// Solve one point (all lanes of the wave call this; the Newton loop exits
+// when a ballot shows every lane done). eps, an: this lane's LDS staging
+// (component c at [c * kBlock]). Returns the number of Newton updates, or
+// -1 (not converged within max_iter, or invalid input). Outputs sigma,
+// a_{n+1} and, if TANGENT, the packed consistent tangent C[21].
+template <class Model, bool TANGENT>
+__device__ __forceinline__ int solve_point(const PhaseConst<Model> &pc, bool valid, const double *eps,
+                                           const double *an, double h, double tol, int max_iter,
+                                           unsigned flags, double *sig, double *anew, double *C) {
+    const typename Model::Phase &prm = pc.prm;
+    const bool newton = valid && Model::flows(prm);
+
+    double D[6] = {0, 0, 0, 0, 0, 0};
+    Resid2 cur;
+    double phi = 0.0;
+    int status = valid ? 0 : -1;
+    if (newton) {
+        residual2<Model>(prm, pc.Kinv, Strided<kBlock>{eps}, Strided<kBlock>{an}, D, h, cur);
+        phi = h * cur.psi;
+    }
+    bool done = !newton;
+    int k = 0;
+    for (;;) {
+        lds_reload_point();
+        if (!done) {
+            bool zero = true;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) zero = zero && (cur.F[c] == 0.0);
+            bool conv = zero;
+            if (!conv && k >= 1) {
+                if (flags & AUTOMAT_SIGMA_CRITERION)
+                    conv = sigma_converged<Model>(prm, Strided<kBlock>{eps}, Strided<kBlock>{an},
+                                                  D, cur.F, tol);
+                else
+                    conv = la::norm_inf6(cur.F) <= tol * la::norm_inf6(D);
+            }
+            if (conv) {
+                done = true;
+                status = k;
+            } else if (k >= max_iter) {
+                done = true;
+                status = -1;
+            }
+        }
+        if (__ballot(!done) == 0) break;
+        if (!done) {
+            // Cholesky factor of M = K^-1 + h Psi'' (from the last residual)
+            double y[6], delta[6], idg[6];
+            const bool spd = la::cholesky6(cur.M, idg);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) y[c] = cur.F[c];
+            la::chol_solve6(cur.M, idg, y);
+            lds_reload_point();
+            if (!spd) {
+                done = true;
+                status = -1;
+            } else {
+                la::symv6(pc.Kinv, y, delta);
+                const double slope = la::dot6(cur.F, y);
+                const double s1 = la::dot6(D, y), s2 = la::dot6(delta, y);
+                const double psi0 = cur.psi;
+                // full step first; a rejected trial D - t delta moves to
+                // D - t/2 delta = (D - t delta) + t/2 delta in place
+                double t = 1.0, dphi;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) D[c] -= delta[c];
+                for (;;) {
+                    lds_reload_point();
+                    residual2<Model>(prm, pc.Kinv, Strided<kBlock>{eps}, Strided<kBlock>{an}, D,
+                                     h, cur);
+                    dphi = -t * s1 + 0.5 * t * t * s2 + h * (cur.psi - psi0);
+                    if (dphi <= -1e-4 * t * slope + 1e-13 * phi || t < 0x1p-30) break;
+                    t *= 0.5;
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) D[c] += t * delta[c];
+                }
+                phi += dphi;
+                ++k;
+            }
+        }
+    }
+    lds_reload_point();
+
+    // outputs
+    double epsv[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        anew[c] = newton ? an[c * kBlock] + D[c] : an[c * kBlock];
+        epsv[c] = eps[c * kBlock];
+    }
+    if (valid) {
+        Model::stress(prm, epsv, anew, sig);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) sig[c] = anew[c] = NAN;
+    }
+    if constexpr (TANGENT) {
+        if (newton) {
+            // M at the converged point came with the last residual
+            double *M = cur.M, idg[6];
+            la::cholesky6(M, idg);
+            double W[6][6];
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                double col[6];
+#pragma unroll
+                for (int r = 0; r < 6; ++r) col[r] = pc.R[r * 6 + j];
+                la::forward6(M, idg, col);
+#pragma unroll
+                for (int r = 0; r < 6; ++r) W[r][j] = col[r];
+            }
+#pragma unroll
+            for (int r = 0; r < 6; ++r)
+#pragma unroll
+                for (int c = 0; c <= r; ++c) {
+                    double s = pc.C0[la::pk(r, c)];
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) s += W[q][r] * W[q][c];
+                    C[la::pk(r, c)] = s;
+                }
+        } else if (valid) {
+#pragma unroll
+            for (int c = 0; c < 21; ++c) C[c] = pc.Cee[c];
+        } else {
+#pragma unroll
+            for (int c = 0; c < 21; ++c) C[c] = NAN;
+        }
+    }
+    return status;
+}
+
+}  // namespace automat

@@ -1,0 +1,607 @@
+// server.hip -- continuous-batching service for material-point evaluation
+// requests (uneven sizes, several load steps each, state kept on the
+// device).
+//
+// Host side: a scheduler thread owns two HIP streams and one device arena
+// of the memory budget. Requests are admitted in arrival order while their
+// device block (phase ids, internal variables, stress: 97 B per point, plus
+// the phase tables) fits in the arena (first-fit, coalescing). Every round
+// builds one batch with the next load step of every admitted request (a
+// ragged table of segments) and launches one kernel over all of them; while
+// it runs, requests that arrived meanwhile are admitted and their inputs
+// uploaded on the second stream (their first batch waits for an event).
+// Finished requests return their block at once. In sequential mode only one
+// request is admitted at a time (one launch and one wait per load step),
+// which is the per-request baseline.
+//
+// Device side: the batch kernel strides a resident grid over the 256-point
+// tiles of all segments. A tile belongs to one segment: the block finds it
+// by binary search, stages that request's phase table in LDS, generates the
+// step's strain for each of its points, loads a_n, runs the same per-point
+// solve as the plain evaluation kernel and writes sigma and a_{n+1} back.
+// Results therefore do not depend on what else is in the batch.
+//
+// Strain of load step j of K at point i: eps = (j / K) E_final + std z,
+// z_c standard normal from Philox4x32-10 (Salmon, Moraes, Dror, Shaw 2011)
+// keyed by the request seed with counter (i_lo, i_hi, j, w), w = 0, 1, and
+// the Box-Muller transform of uniforms (u + 1/2) 2^-32: pairs (u0, u1),
+// (u2, u3) of word 0 and (u0, u1) of word 1 give z_0 .. z_5.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <iterator>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "automat.h"
+#include "gsm_kernel.hpp"
+#include "host_common.hpp"
+
+namespace automat {
+namespace {
+
+using Model = MSGSM;
+using PC = PhaseConst<Model>;
+
+struct Segment {
+    const uint8_t *phase;
+    double *a;
+    double *sigma;
+    const PC *tab;
+    unsigned long long *nonconv;
+    int64_t n;
+    int64_t tile0;  // first batch tile of this segment
+    double E[6];    // macro strain of this step
+    double noise;
+    double h, tol;
+    uint32_t key0, key1;
+    uint32_t step;
+    int32_t max_iter;
+    int32_t n_phases;
+    int32_t reserved;
+};
+
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+// Philox4x32 with 10 rounds
+__device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+    }
+    return c;
+}
+
+__device__ __forceinline__ double u01(uint32_t u) { return ((double)u + 0.5) * 0x1p-32; }
+
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double &z0, double &z1) {
+    const double t = -2.0 * fm::log(u01(a));  // > 0 for u in (0, 1)
+    const double r = t * fm::rsqrt(t);
+    double s, c;
+    sincospi(2.0 * u01(b), &s, &c);
+    z0 = r * c;
+    z1 = r * s;
+}
+
+__global__ void build_tables_kernel(const Model::Phase *raw, int nph, PC *out) {
+    const int k = threadIdx.x;
+    if (k < nph) build_phase_const<Model>(raw[k], out[k], false);
+}
+
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
+void serve_batch_kernel(const Segment *segs, int nseg, int64_t total_tiles) {
+    extern __shared__ double smem_raw[];
+    double *stage = smem_raw;
+    PC *tab = reinterpret_cast<PC *>(smem_raw + 12 * kBlock);
+    __shared__ int seg_of_tile;
+    double *eps = stage + threadIdx.x;
+    double *an = stage + 6 * kBlock + threadIdx.x;
+    for (int64_t t = blockIdx.x; t < total_tiles; t += gridDim.x) {
+        if (threadIdx.x == 0) {
+            int lo = 0, hi = nseg - 1;
+            while (lo < hi) {  // last segment with tile0 <= t
+                const int mid = (lo + hi + 1) / 2;
+                if (segs[mid].tile0 <= t)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            seg_of_tile = lo;
+        }
+        __syncthreads();
+        const Segment &sg = segs[seg_of_tile];
+        {
+            const double *src = reinterpret_cast<const double *>(sg.tab);
+            double *dst = reinterpret_cast<double *>(tab);
+            const int words = sg.n_phases * (int)(sizeof(PC) / sizeof(double));
+            for (int w = threadIdx.x; w < words; w += kBlock) dst[w] = src[w];
+        }
+        __syncthreads();
+        const int64_t i = (t - sg.tile0) * kBlock + threadIdx.x;
+        if (i < sg.n) {
+            const U4 r0 = philox4x32_10(U4{(uint32_t)i, (uint32_t)(i >> 32), sg.step, 0u}, sg.key0,
+                                        sg.key1);
+            const U4 r1 = philox4x32_10(U4{(uint32_t)i, (uint32_t)(i >> 32), sg.step, 1u}, sg.key0,
+                                        sg.key1);
+            double z[6];
+            box_muller(r0.x, r0.y, z[0], z[1]);
+            box_muller(r0.z, r0.w, z[2], z[3]);
+            box_muller(r1.x, r1.y, z[4], z[5]);
+            bool finite_in = true;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                const double e = sg.E[c] + sg.noise * z[c];
+                const double a = sg.a[c * sg.n + i];
+                finite_in = finite_in && isfinite(e) && isfinite(a);
+                eps[c * kBlock] = e;
+                an[c * kBlock] = a;
+            }
+            const int pid = sg.phase[i];
+            const bool valid = pid < sg.n_phases && finite_in;
+            double sig[6], anew[6];
+            const int status = solve_point<Model, false>(tab[valid ? pid : 0], valid, eps, an, sg.h,
+                                                         sg.tol, sg.max_iter, 0u, sig, anew,
+                                                         nullptr);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                sg.sigma[c * sg.n + i] = sig[c];
+                sg.a[c * sg.n + i] = anew[c];
+            }
+            count_failures(sg.nonconv, status < 0);
+        }
+        __syncthreads();
+    }
+}
+
+double now_s(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+size_t round_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// First-fit sub-allocator over one device arena (offsets only; blocks are
+// 256-byte aligned, neighbours coalesce on release).
+class Arena {
+  public:
+    void reset(size_t size) {
+        free_.clear();
+        if (size) free_[0] = size;
+    }
+    bool alloc(size_t bytes, size_t *off) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            const size_t o = it->first, rest = it->second - bytes;
+            free_.erase(it);
+            if (rest) free_[o + bytes] = rest;
+            *off = o;
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        auto next = free_.lower_bound(off);
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == off) {
+                off = prev->first;
+                bytes += prev->second;
+                free_.erase(prev);
+            }
+        }
+        if (next != free_.end() && off + bytes == next->first) {
+            bytes += next->second;
+            free_.erase(next);
+        }
+        free_[off] = bytes;
+    }
+
+  private:
+    std::map<size_t, size_t> free_;  // offset -> length
+};
+
+// Device block of one request, in this order: phase ids, a (6 x n), sigma
+// (6 x n), derived phase table, raw phase parameters, failure counter.
+struct Layout {
+    size_t phase, a, sigma, tab, raw, nonconv, total;
+};
+
+Layout layout_of(int64_t n, int nph) {
+    Layout l;
+    l.phase = 0;
+    l.a = l.phase + round_up((size_t)n);
+    l.sigma = l.a + round_up((size_t)n * 6 * sizeof(double));
+    l.tab = l.sigma + round_up((size_t)n * 6 * sizeof(double));
+    l.raw = l.tab + round_up((size_t)nph * sizeof(PC));
+    l.nonconv = l.raw + round_up((size_t)nph * sizeof(Model::Phase));
+    l.total = l.nonconv + 256;
+    return l;
+}
+
+struct Req {
+    uint64_t id = 0;
+    automat_request r{};
+    Model::Phase raw[AUTOMAT_MAX_PHASES];
+    int32_t nph = 0;
+    size_t off = 0;  // arena offset of the request's block
+    Layout lay{};
+    uint8_t *d_phase = nullptr;
+    double *d_a = nullptr;
+    double *d_sigma = nullptr;
+    PC *d_tab = nullptr;
+    Model::Phase *d_raw = nullptr;
+    unsigned long long *d_nonconv = nullptr;
+    hipEvent_t ready = nullptr;  // uploads and table build done
+    int32_t steps_done = 0;
+    double t_arrival = 0, t_admit = 0, t_done = 0;
+    int32_t status = 0;
+};
+
+}  // namespace
+}  // namespace automat
+
+using namespace automat;
+
+struct automat_server {
+    size_t budget = 0, used = 0;
+    int64_t max_batch_points = 0;
+    int sequential = 0;
+    int device = 0;
+    int grid = 0;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Req *> pending;
+    std::vector<Req *> active;
+    std::deque<automat_result> done;
+    std::thread worker;
+    bool stop = false;
+    uint64_t next_id = 1;
+    std::chrono::steady_clock::time_point t0;
+    hipStream_t stream = nullptr;  // batch kernels and result copies
+    hipStream_t up = nullptr;      // admissions: uploads and table builds
+    char *arena_base = nullptr;
+    Arena arena;
+    Segment *d_segs = nullptr, *h_segs = nullptr;
+    int seg_cap = 0;
+    size_t rr = 0;  // round-robin start among active requests
+    // statistics
+    int64_t launches = 0, updates = 0;
+    double busy_s = 0;
+};
+
+// Under s->mu: move requests from the head of the queue to the active set
+// while their blocks fit in the arena (arrival order, no overtaking).
+static void take_admissible(automat_server *s, std::vector<Req *> &fresh) {
+    const size_t max_active = s->sequential ? 1 : (size_t)1 << 20;
+    while (!s->stop && !s->pending.empty() && s->active.size() < max_active) {
+        Req *q = s->pending.front();
+        if (!s->arena.alloc(q->lay.total, &q->off)) break;
+        s->pending.pop_front();
+        s->used += q->lay.total;
+        s->active.push_back(q);
+        fresh.push_back(q);
+    }
+}
+
+static void finish(automat_server *s, Req *q, int32_t status) {
+    unsigned long long nc = 0;
+    if (status == AUTOMAT_OK) {
+        bool ok = true;
+        if (q->r.sigma_host)
+            ok = ok && hipMemcpyAsync(q->r.sigma_host, q->d_sigma, (size_t)q->r.n * 6 * sizeof(double),
+                                      hipMemcpyDeviceToHost, s->stream) == hipSuccess;
+        if (q->r.a_host)
+            ok = ok && hipMemcpyAsync(q->r.a_host, q->d_a, (size_t)q->r.n * 6 * sizeof(double),
+                                      hipMemcpyDeviceToHost, s->stream) == hipSuccess;
+        ok = ok && hipMemcpyAsync(&nc, q->d_nonconv, sizeof nc, hipMemcpyDeviceToHost, s->stream) ==
+                       hipSuccess;
+        ok = ok && hipStreamSynchronize(s->stream) == hipSuccess;
+        if (!ok) status = AUTOMAT_EHIP;
+    } else if (q->ready) {
+        // the block may still be written by an upload: let it drain first
+        (void)hipEventSynchronize(q->ready);
+    }
+    if (q->ready) (void)hipEventDestroy(q->ready);
+    q->ready = nullptr;
+    q->status = status;
+    q->t_done = now_s(s->t0);
+    automat_result res{};
+    res.id = q->id;
+    res.status = status;
+    res.steps_done = q->steps_done;
+    res.n = q->r.n;
+    res.nonconverged = (int64_t)nc;
+    res.t_arrival = q->t_arrival;
+    res.t_admit = q->t_admit;
+    res.t_done = q->t_done;
+    std::lock_guard<std::mutex> lock(s->mu);
+    s->active.erase(std::find(s->active.begin(), s->active.end(), q));
+    s->arena.release(q->off, q->lay.total);
+    s->used -= q->lay.total;
+    s->done.push_back(res);
+    delete q;
+    s->cv.notify_all();
+}
+
+// Queue the uploads of a freshly admitted request on the admission stream;
+// its first batch waits for the recorded event.
+static int32_t start_upload(automat_server *s, Req *q) {
+    char *b = s->arena_base + q->off;
+    const int64_t n = q->r.n;
+    q->d_phase = reinterpret_cast<uint8_t *>(b + q->lay.phase);
+    q->d_a = reinterpret_cast<double *>(b + q->lay.a);
+    q->d_sigma = reinterpret_cast<double *>(b + q->lay.sigma);
+    q->d_tab = reinterpret_cast<PC *>(b + q->lay.tab);
+    q->d_raw = reinterpret_cast<Model::Phase *>(b + q->lay.raw);
+    q->d_nonconv = reinterpret_cast<unsigned long long *>(b + q->lay.nonconv);
+    q->t_admit = now_s(s->t0);
+    if (hipEventCreateWithFlags(&q->ready, hipEventDisableTiming) != hipSuccess) {
+        q->ready = nullptr;
+        return AUTOMAT_EHIP;
+    }
+    const size_t abytes = (size_t)n * 6 * sizeof(double);
+    bool ok = hipMemcpyAsync(q->d_phase, q->r.phase, (size_t)n, hipMemcpyHostToDevice, s->up) ==
+                  hipSuccess &&
+              (q->r.a_init ? hipMemcpyAsync(q->d_a, q->r.a_init, abytes, hipMemcpyHostToDevice,
+                                            s->up)
+                           : hipMemsetAsync(q->d_a, 0, abytes, s->up)) == hipSuccess &&
+              hipMemsetAsync(q->d_nonconv, 0, sizeof(unsigned long long), s->up) == hipSuccess &&
+              hipMemcpyAsync(q->d_raw, q->raw, (size_t)q->nph * sizeof(Model::Phase),
+                             hipMemcpyHostToDevice, s->up) == hipSuccess;
+    if (ok) {
+        hipLaunchKernelGGL(build_tables_kernel, dim3(1), dim3(64), 0, s->up, q->d_raw, q->nph,
+                           q->d_tab);
+        ok = hipGetLastError() == hipSuccess && hipEventRecord(q->ready, s->up) == hipSuccess;
+    }
+    return ok ? AUTOMAT_OK : AUTOMAT_EHIP;
+}
+
+static void admit(automat_server *s, std::vector<Req *> &fresh) {
+    for (Req *q : fresh) {
+        const int32_t rc = start_upload(s, q);
+        if (rc != AUTOMAT_OK) finish(s, q, rc);
+    }
+    fresh.clear();
+}
+
+static void worker_loop(automat_server *s) {
+    (void)hipSetDevice(s->device);
+    std::vector<Req *> batch, fresh;
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lock(s->mu);
+            s->cv.wait(lock, [&] { return s->stop || !s->pending.empty() || !s->active.empty(); });
+            if (s->stop && s->active.empty()) {
+                for (Req *q : s->pending) {
+                    automat_result res{};
+                    res.id = q->id;
+                    res.status = AUTOMAT_EINVAL;
+                    res.t_arrival = q->t_arrival;
+                    res.t_done = now_s(s->t0);
+                    s->done.push_back(res);
+                    delete q;
+                }
+                s->pending.clear();
+                return;
+            }
+            take_admissible(s, fresh);
+        }
+        admit(s, fresh);
+        // one batch: the next load step of active requests, round-robin
+        // from s->rr while the point budget lasts (at least one request)
+        batch.clear();
+        {
+            std::lock_guard<std::mutex> lock(s->mu);
+            const size_t na = s->active.size();
+            int64_t pts = 0;
+            for (size_t k = 0; k < na; ++k) {
+                Req *q = s->active[(s->rr + k) % na];
+                if (!batch.empty() && s->max_batch_points > 0 && pts + q->r.n > s->max_batch_points)
+                    continue;
+                batch.push_back(q);
+                pts += q->r.n;
+            }
+            if (na) s->rr = (s->rr + batch.size()) % na;
+        }
+        if (batch.empty()) continue;
+        if ((int)batch.size() > s->seg_cap) {
+            if (s->d_segs) (void)hipFree(s->d_segs);
+            if (s->h_segs) (void)hipHostFree(s->h_segs);
+            s->seg_cap = std::max<int>((int)batch.size(), 2 * s->seg_cap);
+            if (hipMalloc(&s->d_segs, s->seg_cap * sizeof(Segment)) != hipSuccess ||
+                hipHostMalloc(&s->h_segs, s->seg_cap * sizeof(Segment), hipHostMallocDefault) !=
+                    hipSuccess) {
+                s->seg_cap = 0;
+                s->d_segs = nullptr;
+                s->h_segs = nullptr;
+                for (Req *q : batch) finish(s, q, AUTOMAT_ENOMEM);
+                continue;
+            }
+        }
+        int64_t tiles = 0;
+        bool ok = true;
+        for (size_t k = 0; k < batch.size(); ++k) {
+            Req *q = batch[k];
+            if (q->steps_done == 0)
+                ok = ok && hipStreamWaitEvent(s->stream, q->ready, 0) == hipSuccess;
+            Segment &g = s->h_segs[k];
+            g.phase = q->d_phase;
+            g.a = q->d_a;
+            g.sigma = q->d_sigma;
+            g.tab = q->d_tab;
+            g.nonconv = q->d_nonconv;
+            g.n = q->r.n;
+            g.tile0 = tiles;
+            const int32_t step = q->steps_done + 1;
+            for (int c = 0; c < 6; ++c) g.E[c] = q->r.E_final[c] * ((double)step / q->r.steps);
+            g.noise = q->r.noise_std;
+            g.h = q->r.h;
+            g.tol = q->r.tol;
+            g.key0 = (uint32_t)q->r.seed;
+            g.key1 = (uint32_t)(q->r.seed >> 32);
+            g.step = (uint32_t)step;
+            g.max_iter = q->r.max_iter;
+            g.n_phases = q->nph;
+            g.reserved = 0;
+            tiles += (q->r.n + kBlock - 1) / kBlock;
+        }
+        const double tb = now_s(s->t0);
+        ok = ok && hipMemcpyAsync(s->d_segs, s->h_segs, batch.size() * sizeof(Segment),
+                                  hipMemcpyHostToDevice, s->stream) == hipSuccess;
+        const size_t smem = 12 * kBlock * sizeof(double) + AUTOMAT_MAX_PHASES * sizeof(PC);
+        const int grid = (int)std::min<int64_t>(tiles, (int64_t)s->grid);
+        if (ok) {
+            hipLaunchKernelGGL(serve_batch_kernel, dim3(grid), dim3(kBlock), smem, s->stream,
+                               s->d_segs, (int)batch.size(), tiles);
+            ok = hipGetLastError() == hipSuccess;
+        }
+        // admissions of requests that arrived meanwhile overlap the batch
+        {
+            std::lock_guard<std::mutex> lock(s->mu);
+            take_admissible(s, fresh);
+        }
+        admit(s, fresh);
+        ok = hipStreamSynchronize(s->stream) == hipSuccess && ok;
+        s->busy_s += now_s(s->t0) - tb;
+        s->launches += 1;
+        for (Req *q : batch) {
+            q->steps_done += 1;
+            s->updates += q->r.n;
+            if (!ok || q->steps_done >= q->r.steps) finish(s, q, ok ? AUTOMAT_OK : AUTOMAT_EHIP);
+        }
+    }
+}
+
+extern "C" int32_t automat_server_create(size_t hbm_budget_bytes, int64_t max_batch_points,
+                                         int32_t sequential, automat_server **out) {
+    if (!out || hbm_budget_bytes < 4096 || max_batch_points < 0) return AUTOMAT_EINVAL;
+    *out = nullptr;
+    automat_server *s = new (std::nothrow) automat_server();
+    if (!s) return AUTOMAT_ENOMEM;
+    s->budget = hbm_budget_bytes & ~(size_t)255;
+    s->max_batch_points = max_batch_points;
+    s->sequential = sequential ? 1 : 0;
+    s->t0 = std::chrono::steady_clock::now();
+    int cus = 0;
+    int32_t rc = AUTOMAT_OK;
+    if (hipGetDevice(&s->device) != hipSuccess || device_cus(&cus) != AUTOMAT_OK ||
+        hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&s->up, hipStreamNonBlocking) != hipSuccess)
+        rc = AUTOMAT_EHIP;
+    else if (hipMalloc(&s->arena_base, s->budget) != hipSuccess)
+        rc = AUTOMAT_ENOMEM;
+    if (rc != AUTOMAT_OK) {
+        (void)hipGetLastError();
+        if (s->stream) (void)hipStreamDestroy(s->stream);
+        if (s->up) (void)hipStreamDestroy(s->up);
+        delete s;
+        return rc;
+    }
+    s->arena.reset(s->budget);
+    int per_cu = 0;
+    const size_t smem = 12 * kBlock * sizeof(double) + AUTOMAT_MAX_PHASES * sizeof(PC);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, serve_batch_kernel, kBlock, smem) !=
+            hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    s->grid = cus * per_cu;
+    s->worker = std::thread(worker_loop, s);
+    *out = s;
+    return AUTOMAT_OK;
+}
+
+extern "C" int32_t automat_server_submit(automat_server *s, const automat_request *req,
+                                         uint64_t *id) {
+    if (!s || !req || !id) return AUTOMAT_EINVAL;
+    if (req->n < 1 || !req->phase || req->steps < 1 || req->max_iter < 1) return AUTOMAT_EINVAL;
+    if (!std::isfinite(req->h) || !(req->h > 0.0) || !(req->tol > 0.0) || !(req->noise_std >= 0.0))
+        return AUTOMAT_EINVAL;
+    Req *q = new (std::nothrow) Req();
+    if (!q) return AUTOMAT_ENOMEM;
+    q->r = *req;
+    const int32_t rc = copy_params(&req->params, q->raw, &q->nph);
+    if (rc) {
+        delete q;
+        return rc;
+    }
+    q->lay = layout_of(req->n, q->nph);
+    if (q->lay.total > s->budget) {
+        delete q;
+        return AUTOMAT_EBUDGET;
+    }
+    std::lock_guard<std::mutex> lock(s->mu);
+    if (s->stop) {
+        delete q;
+        return AUTOMAT_EINVAL;
+    }
+    q->id = s->next_id++;
+    q->t_arrival = req->t_arrival >= 0.0 ? req->t_arrival : now_s(s->t0);
+    s->pending.push_back(q);
+    *id = q->id;
+    s->cv.notify_all();
+    return AUTOMAT_OK;
+}
+
+extern "C" int32_t automat_server_poll(automat_server *s, automat_result *out, int32_t max,
+                                       int32_t *count) {
+    if (!s || !count || (max > 0 && !out)) return AUTOMAT_EINVAL;
+    std::lock_guard<std::mutex> lock(s->mu);
+    int32_t k = 0;
+    while (k < max && !s->done.empty()) {
+        out[k++] = s->done.front();
+        s->done.pop_front();
+    }
+    *count = k;
+    return AUTOMAT_OK;
+}
+
+extern "C" int32_t automat_server_stats(automat_server *s, automat_server_stats_t *st) {
+    if (!s || !st) return AUTOMAT_EINVAL;
+    std::lock_guard<std::mutex> lock(s->mu);
+    st->clock_s = now_s(s->t0);
+    st->pending = (int64_t)s->pending.size();
+    st->active = (int64_t)s->active.size();
+    st->used_bytes = (int64_t)s->used;
+    st->launches = s->launches;
+    st->updates = s->updates;
+    st->busy_s = s->busy_s;
+    return AUTOMAT_OK;
+}
+
+extern "C" int32_t automat_server_destroy(automat_server *s) {
+    if (!s) return AUTOMAT_OK;
+    {
+        std::lock_guard<std::mutex> lock(s->mu);
+        s->stop = true;
+        s->cv.notify_all();
+    }
+    if (s->worker.joinable()) s->worker.join();
+    (void)hipStreamSynchronize(s->up);
+    (void)hipStreamSynchronize(s->stream);
+    for (Req *q : s->active) {
+        if (q->ready) (void)hipEventDestroy(q->ready);
+        delete q;
+    }
+    if (s->d_segs) (void)hipFree(s->d_segs);
+    if (s->h_segs) (void)hipHostFree(s->h_segs);
+    if (s->arena_base) (void)hipFree(s->arena_base);
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+    if (s->up) (void)hipStreamDestroy(s->up);
+    delete s;
+    return AUTOMAT_OK;
+}

@@ -260,3 +260,99 @@ def points_c1(seed: int = 1, N: int = 256) -> PointSet:
     a_old = deviatoric_draw(n, 1e-4, rng)
     a_old[:, phase != 0] = 0.0
     return PointSet(eps, a_old, phase, config_phases())
+
+
+# ----------------------------------------------------------------------------
+# counter-based strain generator of the serving path (Philox4x32-10)
+# ----------------------------------------------------------------------------
+
+_M32 = np.uint64(0xFFFFFFFF)
+
+
+def philox4x32_10(c0, c1, c2, c3, k0, k1):
+    """Philox4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw 2011), vectorized
+    over counters; returns four uint32 arrays."""
+    c = [np.asarray(x, dtype=np.uint64) & _M32 for x in (c0, c1, c2, c3)]
+    k0, k1 = np.uint64(k0) & _M32, np.uint64(k1) & _M32
+    M0, M1 = np.uint64(0xD2511F53), np.uint64(0xCD9E8D57)
+    W0, W1 = np.uint64(0x9E3779B9), np.uint64(0xBB67AE85)
+    for r in range(10):
+        if r:
+            k0 = (k0 + W0) & _M32
+            k1 = (k1 + W1) & _M32
+        p0 = M0 * c[0]
+        p1 = M1 * c[2]
+        c = [(p1 >> np.uint64(32)) ^ c[1] ^ k0, p1 & _M32, (p0 >> np.uint64(32)) ^ c[3] ^ k1,
+             p0 & _M32]
+    return [x.astype(np.uint32) for x in c]
+
+
+def _u01(u):
+    return (u.astype(np.float64) + 0.5) * 2.0 ** -32
+
+
+def _box_muller(a, b):
+    r = np.sqrt(-2.0 * np.log(_u01(a)))
+    t = 2.0 * np.pi * _u01(b)
+    return r * np.cos(t), r * np.sin(t)
+
+
+def served_strain(n, step, steps, E_final, noise_std, seed):
+    """Strain of load step `step` (1-based) of `steps` at points 0..n-1:
+    (step / steps) E_final + noise_std z, z from Philox4x32-10 keyed by the
+    seed with counter (i_lo, i_hi, step, w) and Box-Muller pairs."""
+    i = np.arange(n, dtype=np.uint64)
+    lo, hi = i & _M32, i >> np.uint64(32)
+    k0, k1 = int(seed) & 0xFFFFFFFF, (int(seed) >> 32) & 0xFFFFFFFF
+    r0 = philox4x32_10(lo, hi, np.uint64(step), np.uint64(0), k0, k1)
+    r1 = philox4x32_10(lo, hi, np.uint64(step), np.uint64(1), k0, k1)
+    z = np.empty((6, n))
+    z[0], z[1] = _box_muller(r0[0], r0[1])
+    z[2], z[3] = _box_muller(r0[2], r0[3])
+    z[4], z[5] = _box_muller(r1[0], r1[1])
+    E = np.asarray(E_final, dtype=np.float64) * (step / steps)
+    return E[:, None] + noise_std * z
+
+
+@dataclass
+class ServeRequest:
+    side: int
+    structure: str          # "fibre" or "sphere"
+    structure_seed: int
+    phases: list
+    steps: int
+    seed: int
+    arrival: float          # seconds after the start of the run
+    E_final: tuple = (5e-3, 0.0, 0.0, 0.0, 0.0, 0.0)
+    noise_std: float = 2e-4
+    h: float = 0.1
+
+    @property
+    def n(self):
+        return self.side ** 3
+
+
+def serving_requests(count=1000, rate=200.0, seed=4, min_side=32, max_side=256):
+    """The request stream of the serving workload: exponential inter-arrival
+    times (rate per second), cube side log-uniform in [min_side, max_side],
+    fibre (as the 256^3 batch) or sphere (20 %, r = 6) structure by a fair
+    coin, every parameter of both phases jittered by U(0.9, 1.1), 1..10 load
+    steps, a strain seed per request."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for k in range(count):
+        t += rng.exponential(1.0 / rate)
+        side = int(round(math.exp(rng.uniform(math.log(min_side), math.log(max_side)))))
+        kind = "fibre" if rng.random() < 0.5 else "sphere"
+        out.append(ServeRequest(side=side, structure=kind, structure_seed=int(rng.integers(1 << 31)),
+                                phases=jitter_phases(config_phases(), rng),
+                                steps=int(rng.integers(1, 11)), seed=int(rng.integers(1 << 62)),
+                                arrival=t))
+    return out
+
+
+def request_phase_field(req: ServeRequest) -> np.ndarray:
+    if req.structure == "fibre":
+        return fibre_phase(req.side, seed=req.structure_seed)
+    return sphere_phase(req.side, seed=req.structure_seed)

@@ -1,0 +1,158 @@
+"""Continuous-batching service on the GPU: each request's final fields equal
+the oracle's run of the same load steps on the reproduced strains, and a
+request's results do not depend on what it was batched with."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2006_04391_amd import inputs
+from tests.test_parity_gpu import TOL, rel_per_point
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _server(**kw):
+    from paper_2006_04391_amd import api
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    return api.Server(kw.pop("budget", 8 << 30), **kw)
+
+
+def _drain(srv, ids, timeout=60.0):
+    got = {}
+    t0 = time.time()
+    while len(got) < len(ids):
+        for r in srv.poll():
+            got[r["id"]] = r
+        assert time.time() - t0 < timeout, "requests did not finish"
+        time.sleep(0.002)
+    return [got[i] for i in ids]
+
+
+def _request(side, structure, seed, steps, phases=None, noise=2e-4, E=(5e-3, 0, 0, 0, 0, 0)):
+    rng = np.random.default_rng(seed)
+    # inclusions scaled to the small test cells
+    phase = (inputs.fibre_phase(side, seed=seed, radius=max(1.0, side / 12), length=side / 2)
+             if structure == "fibre" else
+             inputs.sphere_phase(side, seed=seed, radius=max(1.5, side / 6)))
+    ph = phases if phases is not None else inputs.jitter_phases(inputs.config_phases(), rng)
+    return dict(phase=phase, phases=ph, steps=steps, E_final=E, noise_std=noise,
+                seed=int(rng.integers(1 << 62)))
+
+
+def _oracle_final(q, h=0.1, max_iter=50):
+    n = q["phase"].size
+    a = np.zeros((6, n))
+    fails = 0
+    for j in range(1, q["steps"] + 1):
+        eps = inputs.served_strain(n, j, q["steps"], q["E_final"], q["noise_std"], q["seed"])
+        r = oracle.evaluate(eps, a, q["phase"], q["phases"], h=h, tol=1e-12, max_iter=max_iter)
+        a = r["a_out"]
+        fails += int((r["iters"] < 0).sum())
+    return r["sigma"], a, fails
+
+
+def _check(res, sig_ref, a_ref):
+    assert rel_per_point(res["sigma"], sig_ref).max() <= TOL
+    assert rel_per_point(res["a"], a_ref).max() <= TOL
+
+
+def test_single_request_matches_oracle():
+    q = _request(12, "sphere", 3, 4)
+    srv = _server()
+    rid = srv.submit(**q, want_fields=True)
+    (res,) = _drain(srv, [rid])
+    srv.close()
+    assert res["status"] == 0 and res["steps_done"] == 4 and res["n"] == 12 ** 3
+    sig, a, fails = _oracle_final(q)
+    assert res["nonconverged"] == fails == 0
+    _check(res, sig, a)
+    assert np.abs(a).max() > 0
+    assert res["t_arrival"] <= res["t_admit"] <= res["t_done"]
+
+
+def test_batched_mix_matches_oracle_and_running_alone():
+    reqs = [_request(s, k, 10 + j, steps) for j, (s, k, steps) in
+            enumerate([(9, "fibre", 3), (17, "sphere", 1), (13, "fibre", 5), (10, "sphere", 2),
+                       (21, "fibre", 4), (8, "sphere", 3)])]
+    srv = _server()
+    ids = [srv.submit(**q, want_fields=True) for q in reqs]
+    mixed = _drain(srv, ids)
+    st = srv.stats()
+    srv.close()
+    assert st["updates"] == sum(q["phase"].size * q["steps"] for q in reqs)
+    assert st["used_bytes"] == 0 and st["active"] == 0 and st["pending"] == 0
+    # several requests shared launches
+    assert st["launches"] < sum(q["steps"] for q in reqs)
+    seq = _server(sequential=True)
+    ids = [seq.submit(**q, want_fields=True) for q in reqs]
+    alone = _drain(seq, ids)
+    st = seq.stats()
+    seq.close()
+    assert st["launches"] == sum(q["steps"] for q in reqs)
+    for q, m, s in zip(reqs, mixed, alone):
+        assert m["status"] == s["status"] == 0
+        assert np.array_equal(m["sigma"], s["sigma"]) and np.array_equal(m["a"], s["a"])
+        sig, a, fails = _oracle_final(q)
+        assert m["nonconverged"] == fails
+        _check(m, sig, a)
+
+
+def test_point_cap_splits_batches():
+    reqs = [_request(s, "sphere", 30 + s, 2) for s in (8, 12, 16)]
+    srv = _server(max_batch_points=16 ** 3)
+    ids = [srv.submit(**q, want_fields=True) for q in reqs]
+    out = _drain(srv, ids)
+    st = srv.stats()
+    srv.close()
+    assert st["launches"] >= 4
+    for q, r in zip(reqs, out):
+        sig, a, _ = _oracle_final(q)
+        _check(r, sig, a)
+
+
+def test_budget_admission_and_rejection():
+    from paper_2006_04391_amd import _lib
+    q = _request(16, "fibre", 5, 3)
+    fp = 16 ** 3 * 97 + 8192
+    srv = _server(budget=fp)                   # room for about one request at a time
+    ids = [srv.submit(**q, want_fields=True) for _ in range(3)]
+    out = _drain(srv, ids)
+    for r in out[1:]:
+        assert np.array_equal(r["sigma"], out[0]["sigma"])
+        assert r["t_admit"] >= out[0]["t_done"] - 1e-3
+    big = _request(24, "sphere", 6, 1)
+    with pytest.raises(_lib.AutomatError) as e:
+        srv.submit(**big)
+    assert e.value.code == _lib.EBUDGET
+    srv.close()
+
+
+def test_nonconverged_points_are_counted():
+    ph = inputs.paper_phases()
+    q = _request(10, "sphere", 7, 2, phases=ph, E=(2e-2, 0, 0, 0, 0, 0))
+    srv = _server()
+    rid = srv.submit(**q, want_fields=True, max_iter=2)
+    (res,) = _drain(srv, [rid])
+    srv.close()
+    _, _, fails = _oracle_final(q, max_iter=2)
+    assert fails > 0 and res["nonconverged"] == fails
+
+
+def test_invalid_requests():
+    from paper_2006_04391_amd import _lib
+    q = _request(6, "sphere", 8, 1)
+    srv = _server()
+    for bad in (dict(steps=0), dict(noise_std=-1.0), dict(h=0.0)):
+        with pytest.raises(_lib.AutomatError):
+            srv.submit(**(q | bad))
+    bad_phase = q["phases"] + [dict(q["phases"][0], nu=0.6)]
+    with pytest.raises(_lib.AutomatError):
+        srv.submit(**(q | dict(phases=bad_phase)))
+    rid = srv.submit(**q)
+    (res,) = _drain(srv, [rid])
+    assert res["status"] == 0 and "sigma" not in res
+    srv.close()
