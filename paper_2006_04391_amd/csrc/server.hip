@@ -69,6 +69,8 @@ struct Segment {
     int32_t reserved;
 };
 
+static_assert(sizeof(Segment) % sizeof(double) == 0, "Segment is copied as doubles");
+
 struct U4 {
     uint32_t x, y, z, w;
 };
@@ -104,36 +106,49 @@ __global__ void build_tables_kernel(const Model::Phase *raw, int nph, PC *out) {
     if (k < nph) build_phase_const<Model>(raw[k], out[k], false);
 }
 
+// Segments per launch: their first-tile indices are staged in LDS.
+constexpr int kMaxSegs = 2048;
+
+size_t serve_smem_bytes() {
+    return 12 * kBlock * sizeof(double) + AUTOMAT_MAX_PHASES * sizeof(PC) + sizeof(Segment) +
+           (kMaxSegs + 1) * sizeof(int32_t);
+}
+
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
-void serve_batch_kernel(const Segment *segs, int nseg, int64_t total_tiles) {
+void serve_batch_kernel(const Segment *segs, const int32_t *starts, int nseg, int32_t total_tiles) {
     extern __shared__ double smem_raw[];
     double *stage = smem_raw;
     PC *tab = reinterpret_cast<PC *>(smem_raw + 12 * kBlock);
-    __shared__ int seg_of_tile;
+    Segment *cur = reinterpret_cast<Segment *>(tab + AUTOMAT_MAX_PHASES);
+    int32_t *first = reinterpret_cast<int32_t *>(cur + 1);  // [nseg + 1], last = total_tiles
+    for (int k = threadIdx.x; k <= nseg; k += kBlock) first[k] = starts[k];
+    __syncthreads();
     double *eps = stage + threadIdx.x;
     double *an = stage + 6 * kBlock + threadIdx.x;
-    for (int64_t t = blockIdx.x; t < total_tiles; t += gridDim.x) {
-        if (threadIdx.x == 0) {
-            int lo = 0, hi = nseg - 1;
-            while (lo < hi) {  // last segment with tile0 <= t
-                const int mid = (lo + hi + 1) / 2;
-                if (segs[mid].tile0 <= t)
-                    lo = mid;
-                else
-                    hi = mid - 1;
+    int seg = -1;
+    for (int32_t t = blockIdx.x; t < total_tiles; t += gridDim.x) {
+        // tiles of a block ascend, so the owning segment only moves forward;
+        // every lane reads the same LDS words, the result is block-uniform
+        int ns = seg < 0 ? 0 : seg;
+        while (first[ns + 1] <= t) ++ns;
+        if (ns != seg) {
+            __syncthreads();  // every wave is done with the previous segment's table
+            {
+                const double *src = reinterpret_cast<const double *>(segs + ns);
+                double *dst = reinterpret_cast<double *>(cur);
+                for (int w = threadIdx.x; w < (int)(sizeof(Segment) / sizeof(double)); w += kBlock)
+                    dst[w] = src[w];
+                const int nph = segs[ns].n_phases;
+                const double *tsrc = reinterpret_cast<const double *>(segs[ns].tab);
+                double *tdst = reinterpret_cast<double *>(tab);
+                const int words = nph * (int)(sizeof(PC) / sizeof(double));
+                for (int w = threadIdx.x; w < words; w += kBlock) tdst[w] = tsrc[w];
             }
-            seg_of_tile = lo;
+            __syncthreads();
+            seg = ns;
         }
-        __syncthreads();
-        const Segment &sg = segs[seg_of_tile];
-        {
-            const double *src = reinterpret_cast<const double *>(sg.tab);
-            double *dst = reinterpret_cast<double *>(tab);
-            const int words = sg.n_phases * (int)(sizeof(PC) / sizeof(double));
-            for (int w = threadIdx.x; w < words; w += kBlock) dst[w] = src[w];
-        }
-        __syncthreads();
-        const int64_t i = (t - sg.tile0) * kBlock + threadIdx.x;
+        const Segment &sg = *cur;
+        const int64_t i = (int64_t)(t - sg.tile0) * kBlock + threadIdx.x;
         if (i < sg.n) {
             const U4 r0 = philox4x32_10(U4{(uint32_t)i, (uint32_t)(i >> 32), sg.step, 0u}, sg.key0,
                                         sg.key1);
@@ -143,14 +158,17 @@ void serve_batch_kernel(const Segment *segs, int nseg, int64_t total_tiles) {
             box_muller(r0.x, r0.y, z[0], z[1]);
             box_muller(r0.z, r0.w, z[2], z[3]);
             box_muller(r1.x, r1.y, z[4], z[5]);
+            double *a = sg.a;
+            double *sigma = sg.sigma;
+            const int64_t n = sg.n;
             bool finite_in = true;
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
                 const double e = sg.E[c] + sg.noise * z[c];
-                const double a = sg.a[c * sg.n + i];
-                finite_in = finite_in && isfinite(e) && isfinite(a);
+                const double ac = a[c * n + i];
+                finite_in = finite_in && isfinite(e) && isfinite(ac);
                 eps[c * kBlock] = e;
-                an[c * kBlock] = a;
+                an[c * kBlock] = ac;
             }
             const int pid = sg.phase[i];
             const bool valid = pid < sg.n_phases && finite_in;
@@ -160,12 +178,11 @@ void serve_batch_kernel(const Segment *segs, int nseg, int64_t total_tiles) {
                                                          nullptr);
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
-                sg.sigma[c * sg.n + i] = sig[c];
-                sg.a[c * sg.n + i] = anew[c];
+                __builtin_nontemporal_store(sig[c], sigma + c * n + i);
+                a[c * n + i] = anew[c];
             }
             count_failures(sg.nonconv, status < 0);
         }
-        __syncthreads();
     }
 }
 
@@ -231,6 +248,12 @@ Layout layout_of(int64_t n, int nph) {
     l.nonconv = l.raw + round_up((size_t)nph * sizeof(Model::Phase));
     l.total = l.nonconv + 256;
     return l;
+}
+
+// Launch descriptor buffer for cap segments: the segments, then their
+// first-tile indices (cap + 1 int32).
+size_t seg_bytes(int cap) {
+    return (size_t)cap * sizeof(Segment) + (size_t)(cap + 1) * sizeof(int32_t);
 }
 
 struct Req {
@@ -409,7 +432,7 @@ static void worker_loop(automat_server *s) {
             std::lock_guard<std::mutex> lock(s->mu);
             const size_t na = s->active.size();
             int64_t pts = 0;
-            for (size_t k = 0; k < na; ++k) {
+            for (size_t k = 0; k < na && batch.size() < (size_t)kMaxSegs; ++k) {
                 Req *q = s->active[(s->rr + k) % na];
                 if (!batch.empty() && s->max_batch_points > 0 && pts + q->r.n > s->max_batch_points)
                     continue;
@@ -422,9 +445,9 @@ static void worker_loop(automat_server *s) {
         if ((int)batch.size() > s->seg_cap) {
             if (s->d_segs) (void)hipFree(s->d_segs);
             if (s->h_segs) (void)hipHostFree(s->h_segs);
-            s->seg_cap = std::max<int>((int)batch.size(), 2 * s->seg_cap);
-            if (hipMalloc(&s->d_segs, s->seg_cap * sizeof(Segment)) != hipSuccess ||
-                hipHostMalloc(&s->h_segs, s->seg_cap * sizeof(Segment), hipHostMallocDefault) !=
+            s->seg_cap = std::min<int>(kMaxSegs, std::max<int>((int)batch.size(), 2 * s->seg_cap));
+            if (hipMalloc(&s->d_segs, seg_bytes(s->seg_cap)) != hipSuccess ||
+                hipHostMalloc(&s->h_segs, seg_bytes(s->seg_cap), hipHostMallocDefault) !=
                     hipSuccess) {
                 s->seg_cap = 0;
                 s->d_segs = nullptr;
@@ -460,14 +483,21 @@ static void worker_loop(automat_server *s) {
             g.reserved = 0;
             tiles += (q->r.n + kBlock - 1) / kBlock;
         }
+        const int nseg = (int)batch.size();
+        int32_t *h_first = reinterpret_cast<int32_t *>(s->h_segs + s->seg_cap);
+        for (int k = 0; k < nseg; ++k) h_first[k] = (int32_t)s->h_segs[k].tile0;
+        h_first[nseg] = (int32_t)tiles;
         const double tb = now_s(s->t0);
-        ok = ok && hipMemcpyAsync(s->d_segs, s->h_segs, batch.size() * sizeof(Segment),
-                                  hipMemcpyHostToDevice, s->stream) == hipSuccess;
-        const size_t smem = 12 * kBlock * sizeof(double) + AUTOMAT_MAX_PHASES * sizeof(PC);
+        int32_t *d_first = reinterpret_cast<int32_t *>(s->d_segs + s->seg_cap);
+        ok = ok && tiles < INT32_MAX &&
+             hipMemcpyAsync(s->d_segs, s->h_segs, nseg * sizeof(Segment), hipMemcpyHostToDevice,
+                            s->stream) == hipSuccess &&
+             hipMemcpyAsync(d_first, h_first, (nseg + 1) * sizeof(int32_t), hipMemcpyHostToDevice,
+                            s->stream) == hipSuccess;
         const int grid = (int)std::min<int64_t>(tiles, (int64_t)s->grid);
         if (ok) {
-            hipLaunchKernelGGL(serve_batch_kernel, dim3(grid), dim3(kBlock), smem, s->stream,
-                               s->d_segs, (int)batch.size(), tiles);
+            hipLaunchKernelGGL(serve_batch_kernel, dim3(grid), dim3(kBlock), serve_smem_bytes(),
+                               s->stream, s->d_segs, d_first, nseg, (int32_t)tiles);
             ok = hipGetLastError() == hipSuccess;
         }
         // admissions of requests that arrived meanwhile overlap the batch
@@ -514,8 +544,8 @@ extern "C" int32_t automat_server_create(size_t hbm_budget_bytes, int64_t max_ba
     }
     s->arena.reset(s->budget);
     int per_cu = 0;
-    const size_t smem = 12 * kBlock * sizeof(double) + AUTOMAT_MAX_PHASES * sizeof(PC);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, serve_batch_kernel, kBlock, smem) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, serve_batch_kernel, kBlock,
+                                                     serve_smem_bytes()) !=
             hipSuccess ||
         per_cu < 1)
         per_cu = 1;
