@@ -2,12 +2,13 @@
 // GSM evaluation (forward, forward + tangent) and its vector-Jacobian
 // product. See include/automat.h for the contract.
 //
-// Launch shape: one lane per material point, wave64, 256 lanes per block.
-// Fields are structure-of-arrays, so each of the 12 input and 12 output
-// component streams of a wave is one contiguous 512-byte segment. The grid
-// is sized to the resident capacity of the device and strides over 256-point
-// tiles; every block first builds the per-phase constant table in LDS (from
-// the AD Hessian of the free energy), then reuses it for all its tiles.
+// Launch shape: wave64, 256 lanes per block. Fields are structure-of-arrays,
+// so each of the 12 input component streams of a 64-point chunk is one
+// contiguous 512-byte segment. The grid is sized to the resident capacity of
+// the device; every wave strides over 64-point chunks. Every block first
+// builds the per-phase constant table in LDS (from the AD Hessian of the
+// free energy), then reuses it for all its chunks. Points that flow are
+// compacted into full waves for the Newton solve (below).
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -47,29 +48,96 @@ struct EvalArgs {
 #define AUTOMAT_EVAL_WAVES 2
 #endif
 
+// Wave-level compaction. Every wave walks its own sequence of 64-point
+// chunks. Points without flow (elastic phase, invalid input, out of range)
+// are finished at once; flowing points are queued in the wave's LDS ring
+// and the Newton solve runs on 64 queued points at a time, so its lanes are
+// full even where matrix and inclusion voxels alternate along a row. At the
+// end the remaining queue is solved as one partial batch.
+constexpr int kWaves = kBlock / 64;
+constexpr int kRing = 128;  // >= 63 left over + 64 new
+// ring of one wave: eps and a_n component-major [12][kRing] doubles, then
+// the point index [kRing] (int64) and the phase id [kRing] (int32)
+constexpr size_t kRingBytes = 12 * kRing * sizeof(double) + kRing * (sizeof(int64_t) + sizeof(int32_t));
+static_assert(kRingBytes % sizeof(double) == 0, "ring keeps 8-byte alignment");
+
+__host__ __device__ constexpr size_t eval_smem_bytes(int n_phases) {
+    return kWaves * kRingBytes + (size_t)n_phases * sizeof(PC);
+}
+
+// Orders this lane's LDS writes before other lanes' later reads of them
+// (the compiler would otherwise be free to reorder them; the hardware keeps
+// a wave's LDS operations in order).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool TANGENT>
+__device__ __forceinline__ void store_tangent(const EvalArgs &args, int64_t i, const double *C) {
+    const int64_t n = args.n;
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+            __builtin_nontemporal_store(C[la::pk(r, c)], args.tangent + (6 * r + c) * n + i);
+}
+
+// Solve the queued points head .. head + cnt - 1 (cnt <= 64), lane l taking
+// ring slot head + l, and store their results.
+template <bool TANGENT>
+__device__ __forceinline__ void run_batch(const EvalArgs &args, const PC *tab, double *ring,
+                                          const int64_t *ridx, const int32_t *rpid, uint32_t head,
+                                          uint32_t cnt, int lane) {
+    const uint32_t slot = (head + (uint32_t)lane) & (kRing - 1);
+    const bool active = (uint32_t)lane < cnt;
+    const int raw = active ? rpid[slot] : 0;
+    const bool valid = active && raw < args.n_phases;  // invalid inputs carry an id past the table
+    const int pid = valid ? raw : 0;
+    const int64_t i = active ? ridx[slot] : 0;
+    double sig[6], anew[6], C[TANGENT ? 21 : 1];
+    const int status = solve_point<Model, TANGENT, kRing>(tab[pid], valid, ring + slot,
+                                                          ring + 6 * kRing + slot, args.h, args.tol,
+                                                          args.max_iter, args.flags, sig, anew, C);
+    if (active) {
+        const int64_t n = args.n;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) __builtin_nontemporal_store(sig[c], args.sigma + c * n + i);
+        if (args.a_out) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) __builtin_nontemporal_store(anew[c], args.a_out + c * n + i);
+        }
+        if constexpr (TANGENT) store_tangent<TANGENT>(args, i, C);
+        if (args.iters) args.iters[i] = status;
+    }
+    count_failures(args.nonconv, active && status < 0);
+    wave_lds_sync();  // the slots may be refilled next
+}
+
 template <bool TANGENT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(AUTOMAT_EVAL_WAVES)))
 void gsm_eval_kernel(const EvalArgs args) {
     extern __shared__ double smem_raw[];
-    // per-lane staging of eps and a_n, component-major [12][kBlock]
-    double *stage = smem_raw;
-    PC *tab = reinterpret_cast<PC *>(smem_raw + 12 * kBlock);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double *ring = smem_raw + wave * (kRingBytes / sizeof(double));
+    int64_t *ridx = reinterpret_cast<int64_t *>(ring + 12 * kRing);
+    int32_t *rpid = reinterpret_cast<int32_t *>(ridx + kRing);
+    PC *tab = reinterpret_cast<PC *>(smem_raw + kWaves * (kRingBytes / sizeof(double)));
     for (int k = threadIdx.x; k < args.n_phases; k += blockDim.x)
         build_phase_const<Model>(args.phases[k], tab[k], TANGENT);
     __syncthreads();
 
-    double *eps = stage + threadIdx.x;            // eps[c * kBlock]
-    double *an = stage + 6 * kBlock + threadIdx.x;  // an[c * kBlock]
     const int64_t n = args.n;
-    const double h = args.h;
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    // Software pipelining over tiles: the inputs of the next tile are loaded
-    // into registers while the current tile computes, so the load latency is
-    // hidden behind the Newton work instead of stalling each tile's start.
+    const int64_t chunks = (n + 63) / 64;
+    const int64_t stride = (int64_t)gridDim.x * kWaves;
+    // inputs of the next chunk are loaded into registers while the current
+    // one is handled, so their latency hides behind the Newton work
     double nx_e[6], nx_a[6];
     int nx_p = 0;
-    auto prefetch = [&](int64_t j) {
-        if (j < n) {
+    auto prefetch = [&](int64_t ch) {
+        const int64_t j = ch * 64 + lane;
+        if (ch < chunks && j < n) {
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
                 nx_e[c] = __builtin_nontemporal_load(args.eps + c * n + j);
@@ -78,40 +146,87 @@ void gsm_eval_kernel(const EvalArgs args) {
             nx_p = args.phase[j];
         }
     };
-    prefetch((int64_t)blockIdx.x * kBlock + threadIdx.x);
-    for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n; base += stride) {
-        const int64_t i = base + threadIdx.x;
-        if (i >= n) continue;
-
-        bool finite_in = true;
+    // (the tangent kernel keeps those registers for the tangent instead)
+    constexpr bool kPrefetch = !TANGENT;
+    // The tangent kernel writes 36 more components per point; scattered, its
+    // stores cost more than the idle lanes that compaction would save.
+    constexpr bool kCompact = !TANGENT;
+    uint32_t head = 0, tail = 0;  // queue positions (wave-uniform), slot = pos % kRing
+    int64_t ch = (int64_t)blockIdx.x * kWaves + wave;
+    if (kPrefetch) prefetch(ch);
+    for (;;) {
+        const bool more = ch < chunks;
+        if (more) {
+            const int64_t i = ch * 64 + lane;
+            const bool in_range = i < n;
+            if (!kPrefetch) prefetch(ch);
+            double e[6], a[6];
+            bool finite_in = true;
 #pragma unroll
-        for (int c = 0; c < 6; ++c) {
-            finite_in = finite_in && isfinite(nx_e[c]) && isfinite(nx_a[c]);
-            eps[c * kBlock] = nx_e[c];
-            an[c * kBlock] = nx_a[c];
-        }
-        const int pid = nx_p;
-        prefetch(i + stride);
-        const bool valid = pid < args.n_phases && finite_in;
-        const PC &pc = tab[valid ? pid : 0];
-        double sig[6], anew[6], C[21];
-        const int status = solve_point<Model, TANGENT>(pc, valid, eps, an, h, args.tol, args.max_iter,
-                                                       args.flags, sig, anew, C);
+            for (int c = 0; c < 6; ++c) {
+                e[c] = nx_e[c];
+                a[c] = nx_a[c];
+                finite_in = finite_in && isfinite(e[c]) && isfinite(a[c]);
+            }
+            const int pid = nx_p;
+            ch += stride;
+            if (kPrefetch) prefetch(ch);
+            const bool valid = pid < args.n_phases && finite_in;
+            const PC &pc = tab[valid ? pid : 0];
+            // without compaction every point of the chunk goes through the
+            // batch in lane order, which keeps the output stores coalesced
+            const bool queue = kCompact ? in_range && valid && Model::flows(pc.prm) : in_range;
+            if (kCompact && in_range && !queue) {
+                // no flow: a_{n+1} = a_n, elastic stress and stiffness
+                double sig[6];
+                if (valid) {
+                    Model::stress(pc.prm, e, a, sig);
+                } else {
 #pragma unroll
-        for (int c = 0; c < 6; ++c) __builtin_nontemporal_store(sig[c], args.sigma + c * n + i);
-        if (args.a_out) {
-#pragma unroll
-            for (int c = 0; c < 6; ++c) __builtin_nontemporal_store(anew[c], args.a_out + c * n + i);
-        }
-        if constexpr (TANGENT) {
-#pragma unroll
-            for (int r = 0; r < 6; ++r)
+                    for (int c = 0; c < 6; ++c) sig[c] = a[c] = NAN;
+                }
 #pragma unroll
                 for (int c = 0; c < 6; ++c)
-                    __builtin_nontemporal_store(C[la::pk(r, c)], args.tangent + (6 * r + c) * n + i);
+                    __builtin_nontemporal_store(sig[c], args.sigma + c * n + i);
+                if (args.a_out) {
+#pragma unroll
+                    for (int c = 0; c < 6; ++c)
+                        __builtin_nontemporal_store(a[c], args.a_out + c * n + i);
+                }
+                if constexpr (TANGENT) {
+                    double C[21];
+#pragma unroll
+                    for (int c = 0; c < 21; ++c) C[c] = valid ? pc.Cee[c] : NAN;
+                    store_tangent<TANGENT>(args, i, C);
+                }
+                if (args.iters) args.iters[i] = valid ? 0 : -1;
+            }
+            if (kCompact) count_failures(args.nonconv, in_range && !valid);
+            // append the flowing points to the ring
+            const uint64_t mask = __ballot(queue);
+            if (queue) {
+                const uint32_t pos = (uint32_t)__builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                const uint32_t slot = (tail + pos) & (kRing - 1);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    ring[c * kRing + slot] = e[c];
+                    ring[(6 + c) * kRing + slot] = a[c];
+                }
+                ridx[slot] = i;
+                rpid[slot] = valid ? pid : AUTOMAT_MAX_PHASES;
+            }
+            tail += (uint32_t)__popcll(mask);
+            wave_lds_sync();
         }
-        if (args.iters) args.iters[i] = status;
-        count_failures(args.nonconv, status < 0);
+        // a full wave of queued points, or what is left at the end
+        const uint32_t cnt = tail - head;
+        if (cnt >= 64 || (!more && cnt > 0)) {
+            const uint32_t take = cnt < 64 ? cnt : 64;
+            run_batch<TANGENT>(args, tab, ring, ridx, rpid, head, take, lane);
+            head += take;
+        }
+        if (!more && tail == head) break;
     }
 }
 
@@ -136,7 +251,7 @@ static int32_t device_info(DeviceInfo &out) {
         DeviceInfo d;
         if (hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             return AUTOMAT_EHIP;
-        const size_t smem = 12 * kBlock * sizeof(double) + AUTOMAT_MAX_PHASES * sizeof(PC);
+        const size_t smem = eval_smem_bytes(AUTOMAT_MAX_PHASES);
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&d.blocks_fwd, gsm_eval_kernel<false>,
                                                          kBlock, smem) != hipSuccess ||
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&d.blocks_tan, gsm_eval_kernel<true>,
@@ -235,7 +350,7 @@ extern "C" int32_t automat_evaluate_ex(int64_t n, const double *eps_new, const d
     const int64_t tiles = (n + kBlock - 1) / kBlock;
     const int64_t cap = (int64_t)dev.cus * (tangent_out ? dev.blocks_tan : dev.blocks_fwd);
     const int grid = (int)(tiles < cap ? tiles : cap);
-    const size_t smem = 12 * kBlock * sizeof(double) + (size_t)args.n_phases * sizeof(PC);
+    const size_t smem = eval_smem_bytes(args.n_phases);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (tangent_out)
         hipLaunchKernelGGL(gsm_eval_kernel<true>, dim3(grid), dim3(kBlock), smem, s, args);

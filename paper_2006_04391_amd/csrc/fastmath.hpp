@@ -35,12 +35,15 @@
 namespace automat {
 namespace fm {
 
-// Polynomial coefficients and reduction constants live in a small mutable
-// table rather than in the instruction stream: the compiler then loads them
-// (uniform scalar loads) where they are used instead of materializing all of
-// them once per kernel and holding them in ~50 vector registers.
+// Polynomial coefficients and reduction constants live in a small table in
+// the constant address space rather than in the instruction stream: the
+// compiler cannot fold them (the table is externally initialised), so it
+// reads them with uniform scalar loads into scalar registers instead of
+// materializing every constant in vector registers. Scalar loads also stay
+// out of the vector-memory counter, so the math never waits on outstanding
+// field loads or stores.
 #ifndef AUTOMAT_FM_TABLE_SPACE
-#define AUTOMAT_FM_TABLE_SPACE __device__
+#define AUTOMAT_FM_TABLE_SPACE __constant__
 #endif
 #if defined(__HIP_DEVICE_COMPILE__)
 #define AUTOMAT_FM_TABLE static AUTOMAT_FM_TABLE_SPACE

@@ -33,10 +33,10 @@ __device__ __forceinline__ void count_failures(unsigned long long *counter, bool
 
 // Solve one point (all lanes of the wave call this; the Newton loop exits
 // when a ballot shows every lane done). eps, an: this lane's LDS staging
-// (component c at [c * kBlock]). Returns the number of Newton updates, or
+// (component c at [c * S]). Returns the number of Newton updates, or
 // -1 (not converged within max_iter, or invalid input). Outputs sigma,
 // a_{n+1} and, if TANGENT, the packed consistent tangent C[21].
-template <class Model, bool TANGENT>
+template <class Model, bool TANGENT, int S = kBlock>
 __device__ __forceinline__ int solve_point(const PhaseConst<Model> &pc, bool valid, const double *eps,
                                            const double *an, double h, double tol, int max_iter,
                                            unsigned flags, double *sig, double *anew, double *C) {
@@ -45,10 +45,13 @@ __device__ __forceinline__ int solve_point(const PhaseConst<Model> &pc, bool val
 
     double D[6] = {0, 0, 0, 0, 0, 0};
     Resid2 cur;
+    // cur.M holds the Newton matrix of the current point only when have_M:
+    // a trial predicted to end the iteration is evaluated to first order.
+    bool have_M = true;
     double phi = 0.0;
     int status = valid ? 0 : -1;
     if (newton) {
-        residual2<Model>(prm, pc.Kinv, Strided<kBlock>{eps}, Strided<kBlock>{an}, D, h, cur);
+        residual2<Model>(prm, pc.Kinv, Strided<S>{eps}, Strided<S>{an}, D, h, cur);
         phi = h * cur.psi;
     }
     bool done = !newton;
@@ -62,7 +65,7 @@ __device__ __forceinline__ int solve_point(const PhaseConst<Model> &pc, bool val
             bool conv = zero;
             if (!conv && k >= 1) {
                 if (flags & AUTOMAT_SIGMA_CRITERION)
-                    conv = sigma_converged<Model>(prm, Strided<kBlock>{eps}, Strided<kBlock>{an},
+                    conv = sigma_converged<Model>(prm, Strided<S>{eps}, Strided<S>{an},
                                                   D, cur.F, tol);
                 else
                     conv = la::norm_inf6(cur.F) <= tol * la::norm_inf6(D);
@@ -76,9 +79,16 @@ __device__ __forceinline__ int solve_point(const PhaseConst<Model> &pc, bool val
             }
         }
         if (__ballot(!done) == 0) break;
+        if (!done && !have_M) {
+            // the last trial was expected to converge and did not
+            newton_matrix<Model>(prm, pc.Kinv, h, cur);
+            lds_reload_point();
+        }
+        bool first_order = false;
+        double y[6], delta[6];
         if (!done) {
             // Cholesky factor of M = K^-1 + h Psi'' (from the last residual)
-            double y[6], delta[6], idg[6];
+            double idg[6];
             const bool spd = la::cholesky6(cur.M, idg);
 #pragma unroll
             for (int c = 0; c < 6; ++c) y[c] = cur.F[c];
@@ -89,27 +99,44 @@ __device__ __forceinline__ int solve_point(const PhaseConst<Model> &pc, bool val
                 status = -1;
             } else {
                 la::symv6(pc.Kinv, y, delta);
-                const double slope = la::dot6(cur.F, y);
-                const double s1 = la::dot6(D, y), s2 = la::dot6(delta, y);
-                const double psi0 = cur.psi;
-                // full step first; a rejected trial D - t delta moves to
-                // D - t/2 delta = (D - t delta) + t/2 delta in place
-                double t = 1.0, dphi;
+                // quadratic convergence: a step this small relative to the
+                // new iterate leaves a residual far below tol
+                double dn = 0.0, nn = 0.0;
 #pragma unroll
-                for (int c = 0; c < 6; ++c) D[c] -= delta[c];
-                for (;;) {
-                    lds_reload_point();
-                    residual2<Model>(prm, pc.Kinv, Strided<kBlock>{eps}, Strided<kBlock>{an}, D,
-                                     h, cur);
-                    dphi = -t * s1 + 0.5 * t * t * s2 + h * (cur.psi - psi0);
-                    if (dphi <= -1e-4 * t * slope + 1e-13 * phi || t < 0x1p-30) break;
-                    t *= 0.5;
-#pragma unroll
-                    for (int c = 0; c < 6; ++c) D[c] += t * delta[c];
+                for (int c = 0; c < 6; ++c) {
+                    dn = fmax(dn, fabs(delta[c]));
+                    nn = fmax(nn, fabs(D[c] - delta[c]));
                 }
-                phi += dphi;
-                ++k;
+                first_order = dn <= 1e-3 * nn;
             }
+        }
+        // one kind of trial evaluation for the whole wave
+        first_order = __ballot(!done && !first_order) == 0;
+        if (!done) {
+            const double slope = la::dot6(cur.F, y);
+            const double s1 = la::dot6(D, y), s2 = la::dot6(delta, y);
+            const double psi0 = cur.psi;
+            // full step first; a rejected trial D - t delta moves to
+            // D - t/2 delta = (D - t delta) + t/2 delta in place
+            double t = 1.0, dphi;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) D[c] -= delta[c];
+            for (;;) {
+                lds_reload_point();
+                if (first_order)
+                    residual<Model>(prm, Strided<S>{eps}, Strided<S>{an}, D, h, cur);
+                else
+                    residual2<Model>(prm, pc.Kinv, Strided<S>{eps}, Strided<S>{an}, D,
+                                     h, cur);
+                dphi = -t * s1 + 0.5 * t * t * s2 + h * (cur.psi - psi0);
+                if (dphi <= -1e-4 * t * slope + 1e-13 * phi || t < 0x1p-30) break;
+                t *= 0.5;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) D[c] += t * delta[c];
+            }
+            have_M = !first_order;
+            phi += dphi;
+            ++k;
         }
     }
     lds_reload_point();
@@ -118,8 +145,8 @@ __device__ __forceinline__ int solve_point(const PhaseConst<Model> &pc, bool val
     double epsv[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-        anew[c] = newton ? an[c * kBlock] + D[c] : an[c * kBlock];
-        epsv[c] = eps[c * kBlock];
+        anew[c] = newton ? an[c * S] + D[c] : an[c * S];
+        epsv[c] = eps[c * S];
     }
     if (valid) {
         Model::stress(prm, epsv, anew, sig);
@@ -129,7 +156,9 @@ __device__ __forceinline__ int solve_point(const PhaseConst<Model> &pc, bool val
     }
     if constexpr (TANGENT) {
         if (newton) {
-            // M at the converged point came with the last residual
+            // M at the converged point came with the last residual, unless
+            // that was a first-order trial
+            if (!have_M) newton_matrix<Model>(prm, pc.Kinv, h, cur);
             double *M = cur.M, idg[6];
             la::cholesky6(M, idg);
             double W[6][6];

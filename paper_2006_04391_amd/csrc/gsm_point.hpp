@@ -156,6 +156,16 @@ AD_FN void residual2(const typename Model::Phase &prm, const double *Kinv, const
     for (int i = 0; i < 21; ++i) r.M[i] = Kinv[i] + h * r.M[i];
 }
 
+// Newton matrix M = K^-1 + h Psi''(A) at the point of a first-order
+// residual.
+template <class Model>
+AD_FN void newton_matrix(const typename Model::Phase &prm, const double *Kinv, double h,
+                         Resid2 &r) {
+    Model::psi_hess(prm, r.A, r.M);
+#pragma unroll
+    for (int i = 0; i < 21; ++i) r.M[i] = Kinv[i] + h * r.M[i];
+}
+
 // Stress-criterion test: ||d sigma / d a . F||_inf <= tol ||sigma||_inf at
 // a = a_n + D, with both terms from the AD layer.
 template <class Model, class V>
