@@ -36,7 +36,7 @@ BYTES_PER_POINT_TANGENT = BYTES_PER_POINT + 36 * 8            # 481
 # FETCH_SIZE / WRITE_SIZE (scaled by a 1 GiB copy calibration), keyed by the
 # hash of the kernel sources they were taken on; a changed kernel reports
 # traffic null until it is measured again.
-MEASURED_TRAFFIC = {"03d7b0dd077789af": 3.246e9}
+MEASURED_TRAFFIC = {"3931f98b40505044": 3.487e9}
 KERNEL_SOURCES = ["automat.hip", "ad.hpp", "fastmath.hpp", "linalg6.hpp", "msgsm.hpp",
                   "gsm_point.hpp", "gsm_kernel.hpp"]
 
@@ -100,6 +100,40 @@ def cpu_baseline(ps, budget_s=15.0):
         m *= 4
 
 
+def ms_bench(steps, N=128, h=0.1, tol=1e-6):
+    """The basic scheme on the 128^3 sphere microstructure (20 %, r = 6):
+    uniaxial strain path E(t) = 1e-3 t e11, `steps` steps of h, fixed-point
+    tolerance 1e-6; wall time of all steps with the fields resident."""
+    import torch
+    from paper_2006_04391_amd import api, inputs
+    phase = torch.from_numpy(inputs.sphere_phase(N, seed=2)).cuda()
+    n = N ** 3
+    ms = api.MS((N, N, N), inputs.config_phases(), tol=tol, max_iter=5000)
+    eps = torch.zeros((6, n), dtype=torch.float64, device="cuda")
+    a = torch.zeros_like(eps)
+    ms.step(phase, [0.0] * 6, h, eps, a)       # warm-up (plans, modules)
+    eps.zero_()
+    a.zero_()
+    ms.set_macro([0.0] * 6)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = []
+    mean = None
+    for k in range(1, steps + 1):
+        mean, it, _ = ms.step(phase, [1e-3 * h * k, 0, 0, 0, 0, 0], h, eps, a)
+        iters.append(it)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms.close()
+    total = sum(iters)
+    log(f"[bench] MS {N}^3: {steps} steps, {total} iterations, {wall:.2f} s, "
+        f"{wall / total * 1e3:.3f} ms/iteration")
+    return {"workload": f"Moulinec-Suquet basic scheme, {N}^3 periodic spheres (20 %, r=6), "
+                        f"uniaxial strain rate 1e-3/s, {steps} steps of h={h} s, tol {tol}",
+            "wall_s": wall, "iterations": iters, "ms_per_iteration": wall / total * 1e3,
+            "sweep_updates_per_s": total * n / wall, "sigma_mean_last": mean}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +146,8 @@ def main():
                     help="requests in the serving stream (0 skips the serving leg)")
     ap.add_argument("--serve-workers", type=int, default=8,
                     help="host processes generating the requests' microstructures")
+    ap.add_argument("--ms-steps", type=int, default=20,
+                    help="load steps of the 128^3 Moulinec-Suquet run (0 skips it)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (known traffic: 1 GiB read, "
                          "1 GiB written) so profiler byte counters can be scaled")
@@ -209,6 +245,9 @@ def main():
         out["tangent"] = {"ms_per_step": ms_t, "value": n / (ms_t * 1e-3), "unit": "updates/s",
                           "hbm_gbs": BYTES_PER_POINT_TANGENT * n / (ms_t * 1e-3) / 1e9}
         log(f"[bench] tangent: {ms_t:.3f} ms/step")
+
+    if args.ms_steps > 0:
+        out["ms"] = ms_bench(args.ms_steps)
 
     if serve_reqs is not None:
         from paper_2006_04391_amd import serve

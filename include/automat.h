@@ -206,6 +206,41 @@ int32_t automat_ms_set_macro(automat_ms *ms, const double *E_previous);
 /* The reference medium in use. */
 int32_t automat_ms_reference(const automat_ms *ms, double *lambda0, double *mu0);
 
+/* Reverse step: vector-Jacobian product of one converged load step. The
+ * paper obtains tangents by the implicit function theorem applied to the
+ * converged Newton system (section "Implicit Euler", consistent tangent);
+ * here the same theorem is applied one level up, to the converged fixed
+ * point eps = E - Gamma0 (sigma(eps) - C0 eps) of the basic scheme. For the
+ * functional
+ *   L = w . mean(sigma_k) + sum_x grad_sigma(x) . sigma_k(x)
+ *       + sum_x grad_a(x) . a_k(x)
+ * of the step's stress and internal variables, the adjoint field lam solves
+ *   lam = b - (C - C0) Gamma0 lam,   b = direct strain cotangent of L,
+ * with C the consistent tangent field at the converged strain (the same
+ * fixed-point iteration as the forward scheme, in transposed form). Then
+ * dL/dE_k = sum_x lam(x), and the cotangent g + w/n - Gamma0 lam of the
+ * stress, taken through the point-level vector-Jacobian product, gives
+ * dL/da_{k-1} and dL/dp.
+ *   eps    device [6][n]: the step's converged strain (as left by
+ *          automat_ms_step); a_prev, a_next: internal variables before and
+ *          after the step (device [6][n]).
+ *   w      host [6] or NULL; grad_sigma, grad_a: device [6][n] or NULL
+ *          (zero).
+ *   grad_E       host [6], out: dL/dE_k.
+ *   grad_a_prev  device [6][n] or NULL, out: dL/da_{k-1}; must not alias
+ *                an input.
+ *   grad_params  device [n_phases][AUTOMAT_NPAR] or NULL, accumulated:
+ *                dL/dp.
+ *   iters, residual: adjoint iterations and the last relative change
+ *   ||lam' - lam||_2 / ||b||_2; the iteration stops at opts.tol (or runs
+ *   opts.max_iter times with fixed_iter). Work space (54 doubles per
+ *   point) is allocated on the first call. Synchronizes the stream. */
+int32_t automat_ms_adjoint_step(automat_ms *ms, const uint8_t *phase, double h,
+                                const double *eps, const double *a_prev, const double *a_next,
+                                const double *w, const double *grad_sigma, const double *grad_a,
+                                double *grad_E, double *grad_a_prev, double *grad_params,
+                                int32_t *iters, double *residual, void *stream);
+
 int32_t automat_ms_destroy(automat_ms *ms);
 
 /* ------------------------------------------------------------------------

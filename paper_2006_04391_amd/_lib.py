@@ -85,6 +85,8 @@ SIGNATURES = {
     "automat_ms_step": (_i32, [_vp, _vp, _vp, _dbl, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "automat_ms_set_macro": (_i32, [_vp, _vp]),
     "automat_ms_reference": (_i32, [_vp, _vp, _vp]),
+    "automat_ms_adjoint_step": (_i32, [_vp, _vp, _dbl, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                        _vp, _vp, _vp, _vp]),
     "automat_ms_destroy": (_i32, [_vp]),
     "automat_server_create": (_i32, [ctypes.c_size_t, _i64, _i32, _vp]),
     "automat_server_submit": (_i32, [_vp, _vp, _vp]),

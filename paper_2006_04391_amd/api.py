@@ -176,6 +176,37 @@ class MS:
         check("automat_ms_step", rc)
         return list(mean), iters.value, res.value
 
+    def adjoint_step(self, phase, h, eps, a_prev, a_next, w=None, grad_sigma=None, grad_a=None,
+                     grad_a_prev=None, grad_params=None):
+        """Reverse step of one converged load step (automat_ms_adjoint_step).
+        Returns (dL/dE (6,), adjoint iterations, last relative change);
+        grad_a_prev (6, n) receives dL/da_{k-1}, grad_params (n_phases, 7)
+        accumulates dL/dp."""
+        dev = self.device
+        eps = _field(eps, "eps", 6, self.n, dev)
+        a_prev = _field(a_prev, "a_prev", 6, self.n, dev)
+        a_next = _field(a_next, "a_next", 6, self.n, dev)
+        phase = _phase_ids(phase, self.n, dev)
+        if grad_sigma is not None:
+            grad_sigma = _field(grad_sigma, "grad_sigma", 6, self.n, dev)
+        if grad_a is not None:
+            grad_a = _field(grad_a, "grad_a", 6, self.n, dev)
+        if grad_a_prev is not None:
+            grad_a_prev = _field(grad_a_prev, "grad_a_prev", 6, self.n, dev)
+        if grad_params is not None:
+            grad_params = _field(grad_params, "grad_params", len(self.phases), _lib.NPAR, dev)
+        wv = (ctypes.c_double * 6)(*[float(x) for x in w]) if w is not None else None
+        gE = (ctypes.c_double * 6)()
+        iters = ctypes.c_int32()
+        res = ctypes.c_double()
+        with torch.cuda.device(dev):
+            rc = load().automat_ms_adjoint_step(
+                self._h, _ptr(phase), float(h), _ptr(eps), _ptr(a_prev), _ptr(a_next), wv,
+                _ptr(grad_sigma), _ptr(grad_a), gE, _ptr(grad_a_prev), _ptr(grad_params),
+                ctypes.byref(iters), ctypes.byref(res), _stream(dev))
+        check("automat_ms_adjoint_step", rc)
+        return list(gE), iters.value, res.value
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             load().automat_ms_destroy(self._h)
@@ -186,6 +217,57 @@ class MS:
             self.close()
         except Exception:
             pass
+
+
+def ms_gradients(shape, phase, phases, loads, h, **opts):
+    """Run the basic scheme over the load steps `loads` (macro strains E_1..E_K)
+    from zero state, keeping each converged step (strain and internal
+    variables) on the device, then differentiate the last step's mean
+    stress by reverse steps. Returns dict(sigma_mean (6,), dsig_dE (6, K, 6):
+    d mean(sigma_K)_j / d (E_k)_c, dsig_dp (6, n_phases, 7):
+    d mean(sigma_K)_j / d p, forward and adjoint iteration counts)."""
+    import numpy as np
+    ms = MS(shape, phases, **opts)
+    try:
+        n, dev = ms.n, ms.device
+        ph = _phase_ids(torch.as_tensor(np.ascontiguousarray(phase)).to(dev), n, dev)
+        eps = torch.zeros((6, n), dtype=torch.float64, device=dev)
+        a = torch.zeros_like(eps)
+        states = [a.clone()]                 # a_0 .. a_K
+        strains = []                         # eps_1 .. eps_K
+        fwd_iters = []
+        mean = None
+        for E in loads:
+            mean, it, _ = ms.step(ph, E, h, eps, a)
+            strains.append(eps.clone())
+            states.append(a.clone())
+            fwd_iters.append(it)
+        K = len(loads)
+        dE = np.zeros((6, K, 6))
+        dp = np.zeros((6, len(phases), _lib.NPAR))
+        adj_iters = []
+        ga = torch.empty_like(eps)
+        ga_prev = torch.empty_like(eps)
+        for j in range(6):
+            w = [0.0] * 6
+            w[j] = 1.0
+            gp = torch.zeros((len(phases), _lib.NPAR), dtype=torch.float64, device=dev)
+            carry = None
+            for k in range(K - 1, -1, -1):
+                gE, it, _ = ms.adjoint_step(ph, h, strains[k], states[k], states[k + 1],
+                                            w=w if k == K - 1 else None, grad_a=carry,
+                                            grad_a_prev=ga_prev if k > 0 else None,
+                                            grad_params=gp)
+                dE[j, k] = gE
+                adj_iters.append(it)
+                if k > 0:
+                    ga, ga_prev = ga_prev, ga
+                    carry = ga
+            dp[j] = gp.cpu().numpy()
+        return dict(sigma_mean=np.array(mean), dsig_dE=dE, dsig_dp=dp, fwd_iters=fwd_iters,
+                    adj_iters=adj_iters)
+    finally:
+        ms.close()
 
 
 def _phases_from_tensor(params, kinds):

@@ -200,6 +200,71 @@ __global__ void shift_kernel(double *eps, int64_t n, double d0, double d1, doubl
     eps[5 * n + i] += d5;
 }
 
+// lam' = b - (C - C0) t with C the packed-by-rows 6x6 tangent field [36][n]
+// and t = Gamma0 lam (the raw inverse transform, scaled by 1/n here);
+// per-block partial sums of |lam' - lam|^2 and |b|^2; lam <- lam'
+__global__ __launch_bounds__(kRedBlock) void adjoint_update_kernel(
+    double *lam, const double *b, const double *raw, const double *C, int64_t n, double lam0,
+    double mu0, double *partial) {
+    __shared__ double red[2][kRedBlock];
+    const double inv = 1.0 / (double)n;
+    double acc = 0.0, accb = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kRedBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kRedBlock) {
+        double t[6];
+        for (int c = 0; c < 6; ++c) t[c] = raw[c * n + i] * inv;
+        const double tr = lam0 * (t[0] + t[1] + t[2]);
+        for (int r = 0; r < 6; ++r) {
+            double ct = 0.0;
+            for (int c = 0; c < 6; ++c) ct += C[(6 * r + c) * n + i] * t[c];
+            const double c0t = r < 3 ? tr + 2.0 * mu0 * t[r] : mu0 * t[r];
+            const double bv = b[r * n + i];
+            const double nv = bv - (ct - c0t);
+            const double d = nv - lam[r * n + i];
+            acc += d * d;
+            accb += bv * bv;
+            lam[r * n + i] = nv;
+        }
+    }
+    red[0][threadIdx.x] = acc;
+    red[1][threadIdx.x] = accb;
+    __syncthreads();
+    for (int w = kRedBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = red[0][0];
+        partial[gridDim.x + blockIdx.x] = red[1][0];
+    }
+}
+
+// out = g + w / n - raw / n  (g may be null): the stress cotangent that
+// carries the parameter and a_{k-1} sensitivities, g - Gamma0 lam
+__global__ void adjoint_sigma_kernel(double *out, const double *g, const double *raw, int64_t n,
+                                     double w0, double w1, double w2, double w3, double w4,
+                                     double w5) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double inv = 1.0 / (double)n;
+    const double w[6] = {w0, w1, w2, w3, w4, w5};
+    for (int c = 0; c < 6; ++c)
+        out[c * n + i] = (g ? g[c * n + i] : 0.0) + w[c] * inv - raw[c * n + i] * inv;
+}
+
+// out = g + w / n (g may be null)
+__global__ void seed_kernel(double *out, const double *g, int64_t n, double w0, double w1,
+                            double w2, double w3, double w4, double w5) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double inv = 1.0 / (double)n;
+    const double w[6] = {w0, w1, w2, w3, w4, w5};
+    for (int c = 0; c < 6; ++c) out[c * n + i] = (g ? g[c * n + i] : 0.0) + w[c] * inv;
+}
+
 }  // namespace
 }  // namespace automat
 
@@ -217,6 +282,11 @@ struct automat_ms {
     double *partial;            // [6 * kRedBlocks]
     double *scal;               // [8] reduced scalars
     double *host_scal;          // pinned [8]
+    // reverse step work space, allocated on first use
+    double *tan;                // [36][n] consistent tangent at the converged strain
+    double *lam;                // [6][n] adjoint field
+    double *rhs;                // [6][n] right-hand side / scratch
+    double *gs;                 // [6][n] stress cotangent
 };
 
 static int32_t ms_check_opts(const automat_ms_options *o) {
@@ -294,6 +364,10 @@ extern "C" int32_t automat_ms_destroy(automat_ms *m) {
     if (m->partial) (void)hipFree(m->partial);
     if (m->scal) (void)hipFree(m->scal);
     if (m->host_scal) (void)hipHostFree(m->host_scal);
+    if (m->tan) (void)hipFree(m->tan);
+    if (m->lam) (void)hipFree(m->lam);
+    if (m->rhs) (void)hipFree(m->rhs);
+    if (m->gs) (void)hipFree(m->gs);
     delete m;
     return AUTOMAT_OK;
 }
@@ -393,5 +467,110 @@ extern "C" int32_t automat_ms_step(automat_ms *m, const uint8_t *phase, const do
 extern "C" int32_t automat_ms_set_macro(automat_ms *m, const double *E_prev) {
     if (!m || !E_prev) return AUTOMAT_EINVAL;
     for (int c = 0; c < 6; ++c) m->E_prev[c] = E_prev[c];
+    return AUTOMAT_OK;
+}
+
+// Gamma0 applied to a stress-like field x (not modified): the raw inverse
+// transform (n times Gamma0 x, zero mean) lands in m->sig.
+static int32_t ms_gamma(automat_ms *m, const double *x, hipStream_t s) {
+    const int tb = 256;
+    const int nhb = (int)((m->f.nh + tb - 1) / tb);
+    const double c1 = 1.0 / (2.0 * m->mu0);
+    const double c2 = (m->lam0 + m->mu0) / (m->mu0 * (m->lam0 + 2.0 * m->mu0));
+    if (hipMemcpyAsync(m->sig, x, (size_t)m->f.n * 6 * sizeof(double), hipMemcpyDeviceToDevice,
+                       s) != hipSuccess)
+        return AUTOMAT_EHIP;
+    if (hipfftExecD2Z(m->fwd, m->sig, m->spec) != HIPFFT_SUCCESS) return AUTOMAT_EHIP;
+    hipLaunchKernelGGL(gamma_kernel, dim3(nhb), dim3(tb), 0, s, m->spec, m->f, c1, c2, 0.0, 0.0,
+                       0.0, 0.0, 0.0, 0.0);
+    if (hipfftExecZ2D(m->inv, m->spec, m->sig) != HIPFFT_SUCCESS) return AUTOMAT_EHIP;
+    return AUTOMAT_OK;
+}
+
+extern "C" int32_t automat_ms_adjoint_step(automat_ms *m, const uint8_t *phase, double h,
+                                           const double *eps, const double *a_prev,
+                                           const double *a_next, const double *w,
+                                           const double *grad_sigma, const double *grad_a,
+                                           double *grad_E, double *grad_a_prev,
+                                           double *grad_params, int32_t *iters, double *residual,
+                                           void *stream) {
+    if (!m || !phase || !eps || !a_prev || !a_next || !grad_E) return AUTOMAT_EINVAL;
+    if (!std::isfinite(h) || !(h > 0.0)) return AUTOMAT_EINVAL;
+    if (grad_a_prev && (grad_a_prev == grad_a || grad_a_prev == a_prev || grad_a_prev == a_next ||
+                        grad_a_prev == eps))
+        return AUTOMAT_EINVAL;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int64_t n = m->f.n;
+    const size_t fb = (size_t)n * 6 * sizeof(double);
+    if (!m->tan) {
+        if (hipMalloc(&m->tan, 6 * fb) != hipSuccess || hipMalloc(&m->lam, fb) != hipSuccess ||
+            hipMalloc(&m->rhs, fb) != hipSuccess || hipMalloc(&m->gs, fb) != hipSuccess) {
+            (void)hipGetLastError();
+            return AUTOMAT_ENOMEM;
+        }
+    }
+    if (hipfftSetStream(m->fwd, s) != HIPFFT_SUCCESS || hipfftSetStream(m->inv, s) != HIPFFT_SUCCESS)
+        return AUTOMAT_EHIP;
+    const int tb = 256;
+    const int gb = (int)((n + tb - 1) / tb);
+    const int rb = (int)((n + kRedBlock - 1) / kRedBlock) < kRedBlocks
+                       ? (int)((n + kRedBlock - 1) / kRedBlock)
+                       : kRedBlocks;
+    const double wz[6] = {0, 0, 0, 0, 0, 0};
+    const double *wv = w ? w : wz;
+    // consistent tangent field at the converged strain (a_{k-1} fixed)
+    int32_t rc = automat_evaluate_ex(n, eps, a_prev, phase, &m->params, h, m->opts.newton_tol,
+                                     m->opts.newton_max_iter, m->lam, nullptr, m->tan, nullptr,
+                                     nullptr, 0u, stream);
+    if (rc) return rc;
+    // stress cotangent of the functional: g + w / n
+    hipLaunchKernelGGL(seed_kernel, dim3(gb), dim3(tb), 0, s, m->gs, grad_sigma, n, wv[0], wv[1],
+                       wv[2], wv[3], wv[4], wv[5]);
+    // b = direct strain cotangent of the point map (backward kernel)
+    rc = automat_evaluate_backward(n, eps, a_prev, a_next, phase, &m->params, h, m->gs, grad_a,
+                                   m->rhs, nullptr, nullptr, stream);
+    if (rc) return rc;
+    // lam = b - (C - C0) Gamma0 lam, from lam = b
+    if (hipMemcpyAsync(m->lam, m->rhs, fb, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return AUTOMAT_EHIP;
+    int it = 0;
+    double err = 0.0;
+    for (it = 1; it <= m->opts.max_iter; ++it) {
+        rc = ms_gamma(m, m->lam, s);
+        if (rc) return rc;
+        hipLaunchKernelGGL(adjoint_update_kernel, dim3(rb), dim3(kRedBlock), 0, s, m->lam, m->rhs,
+                           m->sig, m->tan, n, m->lam0, m->mu0, m->partial);
+        hipLaunchKernelGGL(finish_kernel, dim3(2), dim3(64), 0, s, m->partial, rb, m->scal);
+        if (!m->opts.fixed_iter || it == m->opts.max_iter) {
+            if (hipMemcpyAsync(m->host_scal, m->scal, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                               s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                return AUTOMAT_EHIP;
+            err = m->host_scal[1] > 0.0 ? sqrt(m->host_scal[0] / m->host_scal[1]) : 0.0;
+            if (!m->opts.fixed_iter && err <= m->opts.tol) break;
+        }
+    }
+    if (it > m->opts.max_iter) it = m->opts.max_iter;
+    // dL/dE = sum_x lam(x)
+    hipLaunchKernelGGL(mean6_kernel, dim3(rb), dim3(kRedBlock), 0, s, m->lam, n, m->partial);
+    hipLaunchKernelGGL(finish_kernel, dim3(6), dim3(64), 0, s, m->partial, rb, m->scal);
+    if (hipMemcpyAsync(m->host_scal, m->scal, 6 * sizeof(double), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return AUTOMAT_EHIP;
+    for (int c = 0; c < 6; ++c) grad_E[c] = m->host_scal[c];
+    if (grad_a_prev || grad_params) {
+        // stress cotangent g + w / n - Gamma0 lam, then the point VJP
+        rc = ms_gamma(m, m->lam, s);
+        if (rc) return rc;
+        hipLaunchKernelGGL(adjoint_sigma_kernel, dim3(gb), dim3(tb), 0, s, m->gs, grad_sigma,
+                           m->sig, n, wv[0], wv[1], wv[2], wv[3], wv[4], wv[5]);
+        rc = automat_evaluate_backward(n, eps, a_prev, a_next, phase, &m->params, h, m->gs, grad_a,
+                                       m->rhs, grad_a_prev, grad_params, stream);
+        if (rc) return rc;
+    }
+    if (iters) *iters = it;
+    if (residual) *residual = err;
+    if (hipGetLastError() != hipSuccess) return AUTOMAT_EHIP;
     return AUTOMAT_OK;
 }

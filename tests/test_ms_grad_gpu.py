@@ -1,0 +1,169 @@
+"""Derivatives of the basic scheme's mean stress (reverse steps through the
+converged load steps) against closed forms and against central differences
+of the oracle's basic scheme."""
+import numpy as np
+import pytest
+
+from oracle import ms as oms
+from paper_2006_04391_amd import inputs
+from tests import _tensor as T
+from tests.test_ms_oracle import ELASTIC, laminate_sigma
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GRAD_INDEX = {"E": 0, "nu": 1, "H": 2, "sigma_y": 3, "sigma0": 4, "eps0": 5, "n": 6}
+
+
+def _grads(shape, phase, phases, loads, h, **opts):
+    from paper_2006_04391_amd import api
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    return api.ms_gradients(shape, phase, phases, loads, h, **opts)
+
+
+def _hooke_voigt(E, nu, e):
+    return T.stress_voigt(T.hooke(E, nu, T.strain_tensor(np.asarray(e, dtype=float))))
+
+
+def test_homogeneous_elastic_cell():
+    """One elastic phase: d<sigma>/dE_K = C, earlier steps do not matter,
+    d<sigma>/dE_Young = sigma / E_Young, d<sigma>/dnu by complex step of
+    the closed form."""
+    shape = (6, 6, 6)
+    Ey, nu = 2500.0, 0.35
+    loads = [[1e-3, -2e-4, 0, 0, 5e-4, 0], [2e-3, -4e-4, 1e-4, 3e-4, 1e-3, -2e-4]]
+    r = _grads(shape, np.zeros(216, np.uint8), [ELASTIC(Ey, nu)], loads, 0.1, tol=1e-13,
+               lambda0=500.0, mu0=300.0)
+    C = np.array([_hooke_voigt(Ey, nu, np.eye(6)[c]).real for c in range(6)]).T
+    np.testing.assert_allclose(r["dsig_dE"][:, -1, :], C, rtol=1e-10, atol=1e-10 * np.abs(C).max())
+    assert np.abs(r["dsig_dE"][:, 0, :]).max() <= 1e-10 * np.abs(C).max()
+    sig = _hooke_voigt(Ey, nu, loads[-1]).real
+    np.testing.assert_allclose(r["dsig_dp"][:, 0, GRAD_INDEX["E"]], sig / Ey, rtol=1e-10,
+                               atol=1e-12 * np.abs(sig).max())
+    dnu = _hooke_voigt(Ey, nu + 1e-30j, loads[-1]).imag / 1e-30
+    np.testing.assert_allclose(r["dsig_dp"][:, 0, GRAD_INDEX["nu"]], dnu, rtol=1e-9,
+                               atol=1e-10 * np.abs(dnu).max())
+    for key in ("H", "sigma_y", "sigma0", "eps0", "n"):
+        assert np.all(r["dsig_dp"][:, 0, GRAD_INDEX[key]] == 0.0), key
+
+
+def test_laminate_effective_stiffness():
+    """Elastic laminate: d<sigma>/dE is the exact laminate stiffness."""
+    nz, ny, nx = 4, 4, 16
+    ph = [ELASTIC(2500.0, 0.35), ELASTIC(72000.0, 0.22)]
+    layer = (np.arange(nx) >= 11).astype(np.uint8)
+    phase = np.broadcast_to(layer[None, None, :], (nz, ny, nx)).reshape(-1).copy()
+    E = [1e-3, 3e-4, -2e-4, 4e-4, -5e-4, 6e-4]
+    r = _grads((nz, ny, nx), phase, ph, [E], 0.1, tol=1e-12, max_iter=20000)
+    C = np.array([laminate_sigma(ph, [11 / 16, 5 / 16], np.eye(6)[c]) for c in range(6)]).T
+    np.testing.assert_allclose(r["dsig_dE"][:, 0, :], C, rtol=1e-7, atol=1e-7 * np.abs(C).max())
+
+
+def _oracle_mean(shape, phase, phases, loads, h, lam0, mu0, iters):
+    n = phase.size
+    eps = np.zeros((6, n))
+    a = np.zeros((6, n))
+    prev = np.zeros(6)
+    for E in loads:
+        r = oms.ms_step(eps, a, phase, phases, shape, E, prev, h, lam0=lam0, mu0=mu0, tol=0.0,
+                        max_iter=iters, fixed_iter=True)
+        eps, a, prev = r["eps"], r["a"], np.asarray(E, dtype=float)
+    return r["sigma_mean"]
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 8), (6, 8, 10)])
+def test_viscoplastic_history_vs_oracle_central_differences(shape):
+    """Three flowing load steps on spheres: d<sigma_3>/dE_3, d<sigma_3>/dE_1
+    and d<sigma_3>/d(E, nu, sigma0, n) of the matrix over the whole history,
+    against central differences (relative step 1e-7) of the oracle's scheme
+    run with a fixed iteration count far past convergence."""
+    from paper_2006_04391_amd import api
+    nz, ny, nx = shape
+    rng = np.random.default_rng(11)
+    phase = (rng.random(nz * ny * nx) < 0.2).astype(np.uint8)
+    ph = inputs.paper_phases()
+    h = 1.0
+    loads = [[2e-3 * k, -5e-4 * k, 0, 0, 3e-4 * k, 0] for k in (1, 2, 3)]
+    r = _grads(shape, phase, ph, loads, h, tol=1e-13, max_iter=5000)
+    assert np.abs(r["dsig_dp"][:, 0, GRAD_INDEX["sigma0"]]).max() > 0   # the matrix flows
+    ms = api.MS(shape, ph)
+    lam0, mu0 = ms.reference()
+    ms.close()
+    iters = 160
+
+    def fd(perturb, step):
+        lp, pp = perturb(step)
+        lm, pm = perturb(-step)
+        return (_oracle_mean(shape, phase, pp, lp, h, lam0, mu0, iters)
+                - _oracle_mean(shape, phase, pm, lm, h, lam0, mu0, iters)) / (2 * step)
+
+    scale = 1e-7 * np.linalg.norm(loads[-1])
+    for k in (2, 0):
+        for c in (0, 1, 4, 5):
+            def pert(d, k=k, c=c):
+                ll = [list(x) for x in loads]
+                ll[k][c] += d
+                return ll, ph
+            g = fd(pert, scale)
+            adj = r["dsig_dE"][:, k, c]
+            assert np.abs(adj - g).max() <= 1e-5 * max(np.abs(g).max(), 1e-3 * np.abs(
+                r["dsig_dE"][:, 2, :]).max()), (k, c, adj, g)
+    for key in ("E", "nu", "sigma0", "n"):
+        p0 = ph[0][key]
+
+        def pert(d, key=key, p0=p0):
+            q = [dict(ph[0]), dict(ph[1])]
+            q[0][key] = p0 + d
+            return loads, q
+        g = fd(pert, 1e-7 * abs(p0))
+        adj = r["dsig_dp"][:, 0, GRAD_INDEX[key]]
+        assert np.abs(adj - g).max() <= 1e-5 * np.abs(g).max(), (key, adj, g)
+
+
+def test_derivative_run_at_64_cubed_against_gpu_differences():
+    """The 64^3 sphere microstructure, five load steps of the strain path
+    1e-3 t e11 (h = 0.1 s): the effective algorithmic tangent d<sigma_5>/dE_5
+    and d<sigma_5>/d(sigma0, n) against central differences of the GPU
+    scheme (tol 1e-13 on both sides)."""
+    from paper_2006_04391_amd import api
+    N = 64
+    phase = inputs.sphere_phase(N, seed=3)
+    ph = inputs.config_phases()
+    h = 0.1
+    loads = [[1e-3 * h * k, 0, 0, 0, 0, 0] for k in range(1, 6)]
+    opts = dict(tol=1e-13, max_iter=5000)
+    r = _grads((N, N, N), phase, ph, loads, h, **opts)
+    ms = api.MS((N, N, N), ph)
+    lam0, mu0 = ms.reference()
+    ms.close()
+
+    def mean_after(loads_, phases_):
+        ms_ = api.MS((N, N, N), phases_, lambda0=lam0, mu0=mu0, **opts)
+        eps = torch.zeros((6, N ** 3), dtype=torch.float64, device="cuda")
+        a = torch.zeros_like(eps)
+        ph_t = torch.from_numpy(phase).cuda()
+        for E in loads_:
+            mean, _, _ = ms_.step(ph_t, E, h, eps, a)
+        ms_.close()
+        return np.array(mean)
+
+    step = 1e-6 * np.linalg.norm(loads[-1])
+    C = r["dsig_dE"][:, -1, :]
+    for c in (0, 1, 3):
+        lp = [list(x) for x in loads]
+        lm = [list(x) for x in loads]
+        lp[-1][c] += step
+        lm[-1][c] -= step
+        g = (mean_after(lp, ph) - mean_after(lm, ph)) / (2 * step)
+        assert np.abs(C[:, c] - g).max() <= 1e-5 * np.abs(C).max(), (c, C[:, c], g)
+    for key in ("sigma0", "n"):
+        p0 = ph[0][key]
+        d = 1e-6 * abs(p0)
+        qp = [dict(ph[0]), dict(ph[1])]
+        qm = [dict(ph[0]), dict(ph[1])]
+        qp[0][key] = p0 + d
+        qm[0][key] = p0 - d
+        g = (mean_after(loads, qp) - mean_after(loads, qm)) / (2 * d)
+        adj = r["dsig_dp"][:, 0, GRAD_INDEX[key]]
+        assert np.abs(adj - g).max() <= 1e-4 * np.abs(g).max(), (key, adj, g)
