@@ -36,17 +36,24 @@ BYTES_PER_POINT_TANGENT = BYTES_PER_POINT + 36 * 8            # 481
 # FETCH_SIZE / WRITE_SIZE (scaled by a 1 GiB copy calibration), keyed by the
 # hash of the kernel sources they were taken on; a changed kernel reports
 # traffic null until it is measured again.
-MEASURED_TRAFFIC = {"3931f98b40505044": 3.487e9}
+MEASURED_TRAFFIC = {}
+# Executed FP64 FLOP per point of the forward kernel on the 256^3 batch
+# (rocprofv3 SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes / points), same keying.
+MEASURED_FP64_FLOP_PER_POINT = {}
 KERNEL_SOURCES = ["automat.hip", "ad.hpp", "fastmath.hpp", "linalg6.hpp", "msgsm.hpp",
                   "gsm_point.hpp", "gsm_kernel.hpp"]
 
 
 def kernel_source_hash():
+    """Hash of the forward kernel's sources and of the build script (its
+    compiler flags change the code too)."""
     import hashlib
     h = hashlib.sha256()
     for fn in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2006_04391_amd", "csrc", fn), "rb") as f:
             h.update(f.read())
+    with open(os.path.join(ROOT, "paper_2006_04391_amd", "build.py"), "rb") as f:
+        h.update(f.read())
     return h.hexdigest()[:16]
 
 
@@ -235,6 +242,12 @@ def main():
             "bytes_per_point": BYTES_PER_POINT,
         },
     }
+    fpp = MEASURED_FP64_FLOP_PER_POINT.get(kernel_source_hash())
+    if fpp is not None:
+        tf = fpp * n / (avg_launch_ms * 1e-3) / 1e12
+        out["roofline"]["fp64"] = {"executed_flop_per_point": fpp, "achieved": tf,
+                                   "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                   "frac": tf / FP64_PEAK_TFLOPS}
 
     if not args.no_tangent:
         def step_t():

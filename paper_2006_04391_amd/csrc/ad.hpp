@@ -47,6 +47,13 @@
 
 #include "fastmath.hpp"
 
+// Derivative propagation may be reassociated: a chain of partials that
+// scales all six tangent components is then multiplied once instead of per
+// component. Only rounding changes (each derivative is a short sum of
+// products); primal values keep their written order because they are also
+// computed in the files that evaluate the potentials.
+#pragma clang fp reassociate(on)
+
 namespace automat {
 namespace ad {
 
@@ -663,3 +670,5 @@ AD_FN void hessian_block6(const E &e, double (&H)[6][6]) {
 
 }  // namespace ad
 }  // namespace automat
+
+#pragma clang fp reassociate(off)

@@ -156,10 +156,37 @@ void gsm_eval_kernel(const EvalArgs args) {
     if (kPrefetch) prefetch(ch);
     for (;;) {
         const bool more = ch < chunks;
-        if (more) {
+        if (more && !kCompact) {
+            // lane order: the chunk's points go straight into ring slots
+            // tail + lane (the in-range lanes are a prefix of the wave), one
+            // component at a time, so nothing is held in registers
             const int64_t i = ch * 64 + lane;
             const bool in_range = i < n;
-            if (!kPrefetch) prefetch(ch);
+            const uint32_t slot = (tail + (uint32_t)lane) & (kRing - 1);
+            if (in_range) {
+                bool finite_in = true;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    const double v = __builtin_nontemporal_load(args.eps + c * n + i);
+                    finite_in = finite_in && isfinite(v);
+                    ring[c * kRing + slot] = v;
+                }
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    const double v = __builtin_nontemporal_load(args.a_old + c * n + i);
+                    finite_in = finite_in && isfinite(v);
+                    ring[(6 + c) * kRing + slot] = v;
+                }
+                const int pid = args.phase[i];
+                ridx[slot] = i;
+                rpid[slot] = (pid < args.n_phases && finite_in) ? pid : AUTOMAT_MAX_PHASES;
+            }
+            tail += (uint32_t)__popcll(__ballot(in_range));
+            ch += stride;
+            wave_lds_sync();
+        } else if (more) {
+            const int64_t i = ch * 64 + lane;
+            const bool in_range = i < n;
             double e[6], a[6];
             bool finite_in = true;
 #pragma unroll

@@ -119,10 +119,14 @@ AD_FN double log(double x) {
     }
     const double s = (m - 1.0) * rcp(m + 1.0);
     const double z = s * s;
-    // 2 atanh(s) = 2 s (1 + z/3 + z^2/5 + ... + z^11/23)
-    double p = T[0];
-#pragma unroll
-    for (int j = 1; j <= 10; ++j) p = ::fma(p, z, T[j]);
+    // 2 atanh(s) = 2 s (1 + z (1/3 + z/5 + ... + z^10/23)); the inner
+    // polynomial by Estrin's scheme (dependency depth 5 instead of 10)
+    const double z2 = z * z, z4 = z2 * z2, z8 = z4 * z4;
+    const double q0 = ::fma(T[9], z, T[10]), q1 = ::fma(T[7], z, T[8]);
+    const double q2 = ::fma(T[5], z, T[6]), q3 = ::fma(T[3], z, T[4]);
+    const double q4 = ::fma(T[1], z, T[2]);
+    const double s0 = ::fma(q1, z2, q0), s1 = ::fma(q3, z2, q2), s2 = ::fma(T[0], z2, q4);
+    const double p = ::fma(s2, z8, ::fma(s1, z4, s0));
     const double lm = ::fma(2.0 * s * z, p, 2.0 * s);
     const double kd = (double)(tiny ? k - 200 : k);
     return ::fma(kd, T[25], ::fma(kd, T[26], lm));
@@ -135,10 +139,16 @@ AD_FN double exp(double x) {
     if (x > 709.8) return HUGE_VAL;
     const double kd = ::rint(x * T[27]);
     const double r = ::fma(-kd, T[26], ::fma(-kd, T[25], x));
-    // Taylor series of e^r to r^13, Horner form
-    double p = T[11];
-#pragma unroll
-    for (int j = 12; j <= 24; ++j) p = ::fma(p, r, T[j]);
+    // Taylor series of e^r to r^13 by Estrin's scheme (coefficient of r^k
+    // is T[24 - k]; dependency depth 5 instead of 13)
+    const double r2 = r * r, r4 = r2 * r2, r8 = r4 * r4;
+    const double q0 = ::fma(T[23], r, T[24]), q1 = ::fma(T[21], r, T[22]);
+    const double q2 = ::fma(T[19], r, T[20]), q3 = ::fma(T[17], r, T[18]);
+    const double q4 = ::fma(T[15], r, T[16]), q5 = ::fma(T[13], r, T[14]);
+    const double q6 = ::fma(T[11], r, T[12]);
+    const double s0 = ::fma(q1, r2, q0), s1 = ::fma(q3, r2, q2), s2 = ::fma(q5, r2, q4);
+    const double t1 = ::fma(q6, r4, s2);
+    const double p = ::fma(t1, r8, ::fma(s1, r4, s0));
     return ::ldexp(p, (int)kd);
 }
 

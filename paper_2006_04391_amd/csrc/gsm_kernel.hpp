@@ -161,25 +161,24 @@ __device__ __forceinline__ int solve_point(const PhaseConst<Model> &pc, bool val
             if (!have_M) newton_matrix<Model>(prm, pc.Kinv, h, cur);
             double *M = cur.M, idg[6];
             la::cholesky6(M, idg);
-            double W[6][6];
+            // C = C0 + R^T M^-1 R one column of M^-1 R at a time (lower
+            // triangle only: the packed result is symmetric exactly)
+#pragma unroll
+            for (int c = 0; c < 21; ++c) C[c] = pc.C0[c];
 #pragma unroll
             for (int j = 0; j < 6; ++j) {
-                double col[6];
+                double x[6];
 #pragma unroll
-                for (int r = 0; r < 6; ++r) col[r] = pc.R[r * 6 + j];
-                la::forward6(M, idg, col);
+                for (int r = 0; r < 6; ++r) x[r] = pc.R[r * 6 + j];
+                la::chol_solve6(M, idg, x);
 #pragma unroll
-                for (int r = 0; r < 6; ++r) W[r][j] = col[r];
-            }
+                for (int r = j; r < 6; ++r) {
+                    double acc = C[la::pk(r, j)];
 #pragma unroll
-            for (int r = 0; r < 6; ++r)
-#pragma unroll
-                for (int c = 0; c <= r; ++c) {
-                    double s = pc.C0[la::pk(r, c)];
-#pragma unroll
-                    for (int q = 0; q < 6; ++q) s += W[q][r] * W[q][c];
-                    C[la::pk(r, c)] = s;
+                    for (int q = 0; q < 6; ++q) acc = fma(pc.R[q * 6 + r], x[q], acc);
+                    C[la::pk(r, j)] = acc;
                 }
+            }
         } else if (valid) {
 #pragma unroll
             for (int c = 0; c < 21; ++c) C[c] = pc.Cee[c];

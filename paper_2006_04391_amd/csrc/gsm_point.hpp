@@ -41,6 +41,8 @@
 #include "linalg6.hpp"
 #include "msgsm.hpp"
 
+#pragma clang fp reassociate(on)
+
 namespace automat {
 
 // Per-phase constants, built on the device from the AD Hessian of omega.
@@ -189,3 +191,5 @@ AD_FN bool sigma_converged(const typename Model::Phase &prm, const V &epsv, cons
 }
 
 }  // namespace automat
+
+#pragma clang fp reassociate(off)

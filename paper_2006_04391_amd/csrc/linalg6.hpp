@@ -7,6 +7,8 @@
 
 #include "ad.hpp"
 
+#pragma clang fp reassociate(on)
+
 namespace automat {
 namespace la {
 
@@ -92,3 +94,5 @@ AD_FN double norm_inf6(const double *x) {
 
 }  // namespace la
 }  // namespace automat
+
+#pragma clang fp reassociate(off)

@@ -24,6 +24,8 @@
 
 #include "ad.hpp"
 
+#pragma clang fp reassociate(on)
+
 namespace automat {
 
 // Six consecutive leaves BASE .. BASE+5.
@@ -281,3 +283,5 @@ struct MSGSM {
 };
 
 }  // namespace automat
+
+#pragma clang fp reassociate(off)

@@ -167,3 +167,21 @@ def test_derivative_run_at_64_cubed_against_gpu_differences():
         g = (mean_after(loads, qp) - mean_after(loads, qm)) / (2 * d)
         adj = r["dsig_dp"][:, 0, GRAD_INDEX[key]]
         assert np.abs(adj - g).max() <= 1e-4 * np.abs(g).max(), (key, adj, g)
+
+
+def test_reverse_step_rejects_aliased_output():
+    from paper_2006_04391_amd import api, _lib
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    shape = (4, 4, 4)
+    ms = api.MS(shape, [ELASTIC(2500.0, 0.35)])
+    z = torch.zeros((6, 64), dtype=torch.float64, device="cuda")
+    ph = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    g = torch.zeros_like(z)
+    with pytest.raises(_lib.AutomatError):
+        ms.adjoint_step(ph, 0.1, z, z, z, grad_a=g, grad_a_prev=g)
+    with pytest.raises(_lib.AutomatError):
+        ms.adjoint_step(ph, 0.0, z, z, z)
+    gE, it, _ = ms.adjoint_step(ph, 0.1, z, z, z, w=[1, 0, 0, 0, 0, 0])
+    assert it >= 1 and gE[0] > 0
+    ms.close()

@@ -173,3 +173,26 @@ def test_green_operator_keeps_fields_real(shape):
     e_full = np.fft.ifftn(full, axes=(1, 2, 3))
     assert np.abs(e_full.imag).max() <= 1e-12 * np.abs(e_full.real).max()
     np.testing.assert_allclose(e_half, e_full.real, rtol=0, atol=1e-12 * np.abs(e_half).max())
+
+
+def test_central_differences_of_the_scheme_give_the_laminate_stiffness():
+    """The derivative reference of the reverse step (central differences of
+    the oracle's scheme run a fixed number of iterations past convergence)
+    reproduces the exact stiffness of an elastic laminate."""
+    nz, ny, nx = 2, 2, 8
+    ph = [ELASTIC(2500.0, 0.35), ELASTIC(72000.0, 0.22)]
+    layer = (np.arange(nx) >= 5).astype(np.uint8)
+    phase = np.broadcast_to(layer[None, None, :], (nz, ny, nx)).reshape(-1).copy()
+    lam0, mu0 = oms.reference_medium(ph)
+    z = np.zeros((6, phase.size))
+    C = np.array([laminate_sigma(ph, [5 / 8, 3 / 8], np.eye(6)[c]) for c in range(6)]).T
+    d = 1e-7
+    for c in range(6):
+        E = np.zeros(6)
+        E[c] = d
+        sp = oms.ms_step(z, z, phase, ph, (nz, ny, nx), E, np.zeros(6), 0.1, lam0=lam0, mu0=mu0,
+                         tol=0.0, max_iter=800, fixed_iter=True)["sigma_mean"]
+        sm = oms.ms_step(z, z, phase, ph, (nz, ny, nx), -E, np.zeros(6), 0.1, lam0=lam0, mu0=mu0,
+                         tol=0.0, max_iter=800, fixed_iter=True)["sigma_mean"]
+        np.testing.assert_allclose((sp - sm) / (2 * d), C[:, c], rtol=1e-7,
+                                   atol=1e-7 * np.abs(C).max())
