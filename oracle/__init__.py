@@ -55,6 +55,11 @@ def lib():
         L.oracle_force_potential.restype = ctypes.c_int
         L.oracle_force_potential.argtypes = [dp, dp, dp, dp, dp]
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_evaluate_rk23.restype = ctypes.c_int
+        L.oracle_evaluate_rk23.argtypes = [ctypes.c_int64, dp, dp, dp, ctypes.c_void_p,
+                                           ctypes.c_int, dp, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_int, dp, dp, dp,
+                                           ctypes.c_void_p, ctypes.c_void_p]
         _lib = L
     return _lib
 
@@ -125,6 +130,31 @@ def backward(eps, a_old, a_new, phase, phases, h, grad_sigma=None, grad_a=None):
     if rc != 0:
         raise ValueError("oracle_backward: invalid arguments")
     return dict(grad_eps=geps, grad_a_old=gan, grad_params=gpar)
+
+
+def evaluate_rk23(eps_n, eps1, a_old, phase, phases, h=0.1, atol=1e-6, rtol=1e-3,
+                  max_steps=100000, tangent=False):
+    """Adaptive Bogacki-Shampine 3(2) evaluation over one load step with the
+    strain moving linearly from eps_n to eps1. Returns dict(sigma, a_out,
+    tangent (36, n) or None, steps (accepted, -1 on failure), rejected)."""
+    eps_n = _f64(eps_n)
+    n = eps_n.shape[1]
+    eps1 = _f64(eps1, (6, n))
+    a_old = _f64(a_old, (6, n))
+    phase = np.ascontiguousarray(phase, dtype=np.uint8)
+    par = params_rows(phases)
+    sigma = np.empty((6, n))
+    a_out = np.empty((6, n))
+    tan = np.empty((36, n)) if tangent else None
+    steps = np.empty(n, dtype=np.int32)
+    rej = np.empty(n, dtype=np.int32)
+    rc = lib().oracle_evaluate_rk23(n, _dp(eps_n), _dp(eps1), _dp(a_old), phase.ctypes.data,
+                                    par.shape[0], _dp(par), h, atol, rtol, max_steps,
+                                    _dp(sigma), _dp(a_out), _dp(tan), steps.ctypes.data,
+                                    rej.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle_evaluate_rk23: invalid arguments")
+    return dict(sigma=sigma, a_out=a_out, tangent=tan, steps=steps, rejected=rej)
 
 
 def force_potential(phase_row, A):

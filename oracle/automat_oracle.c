@@ -646,3 +646,249 @@ int oracle_force_potential(const double *row, const double A[6], double f[6], do
     memcpy(P2, H, sizeof H);
     return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Adaptive explicit Runge-Kutta evaluation (paper: Section "Rosenbrock and
+ * Runge-Kutta Schemes with Adaptive Step Size" and Section "Error Control";
+ * the embedded Bogacki-Shampine 3(2) pair behind MATLAB's ode23, with the
+ * automatic step size control of Hairer, Norsett and Wanner).
+ *
+ * On the load step [t_n, t_n + h] the strain moves linearly,
+ *   eps(s) = eps_n + (s / h) (eps_{n+1} - eps_n),  0 <= s <= h,
+ * and the internal variables follow a' = f(A(eps(s), a)). With the tangent,
+ * the sensitivity Y = d a / d eps_{n+1} (6x6, Y(0) = 0) follows
+ *   Y' = Psi''(A) ((s / h) C - K Y)
+ * and is advanced by the same stages and the same accepted steps (the
+ * combined system of the paper's Theorem "ad_integration_step").
+ *
+ * One step of size dt from (s, y) (k1 is the last stage of the previous
+ * accepted step, first same as last):
+ *   k2 = f(s + dt/2, y + dt/2 k1),  k3 = f(s + 3dt/4, y + 3dt/4 k2),
+ *   y1 = y + dt (2/9 k1 + 1/3 k2 + 4/9 k3),  k4 = f(s + dt, y1),
+ *   yh = y + dt (7/24 k1 + 1/4 k2 + 1/3 k3 + 1/8 k4).
+ * Error measure on stresses: sigma = C (eps(s) - a) (and, with the tangent,
+ * T = C ((s/h) I - Y)),
+ *   err = sqrt(mean over components of ((z1 - zh) / (atol + rtol max(|z0|, |z1|)))^2)
+ * with z0 at the start, z1 and zh from y1 and yh at the end of the step.
+ * The step is accepted when err <= 1. New step size
+ *   dt * min(fmax, max(1/5, 9/10 err^(-1/3))),  fmax = 5, or 1 right after a
+ * rejection; the first try is the whole load step, and a step never passes
+ * s = h. Elastic phases (f = 0) take one step.
+ * ------------------------------------------------------------------------ */
+
+static void rk_rhs(const phase_t *p, const double C[6][6], const double e0[6],
+                   const double de[6], double theta, const double a[6], double k[6],
+                   double P2[6][6])
+{
+    double eps[6], A[6];
+    for (int i = 0; i < 6; ++i) eps[i] = e0[i] + theta * de[i];
+    gen_stress(p, C, eps, a, A);
+    if (p->kind == 0) {
+        for (int i = 0; i < 6; ++i) k[i] = 0.0;
+        if (P2) memset(P2, 0, 36 * sizeof(double));
+        return;
+    }
+    force_potential(p, A, k, P2);
+}
+
+/* tangent stage: Ydot = Psi'' (theta C - K Y) */
+static void rk_rhs_tan(const double P2[6][6], const double C[6][6], const double K[6][6],
+                       double theta, const double Y[36], double KY[36])
+{
+    double B[6][6];
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) {
+            double s = theta * C[i][j];
+            for (int q = 0; q < 6; ++q) s -= K[i][q] * Y[q * 6 + j];
+            B[i][j] = s;
+        }
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) {
+            double s = 0.0;
+            for (int q = 0; q < 6; ++q) s += P2[i][q] * B[q][j];
+            KY[i * 6 + j] = s;
+        }
+}
+
+static double rk_scale(double atol, double rtol, double z0, double z1)
+{
+    return atol + rtol * fmax(fabs(z0), fabs(z1));
+}
+
+/* Returns the number of accepted steps, or -1 (invalid input or more than
+ * max_steps attempts). sigma, a_out [6]; tangent [36] or NULL. */
+static int rk23_point(const phase_t *ph, int nph, int pid, const double eps_n[6],
+                      const double eps1[6], const double an[6], double h, double atol,
+                      double rtol, int max_steps, double sigma[6], double a_out[6],
+                      double *tangent, int *rejected)
+{
+    *rejected = 0;
+    int bad = pid >= nph || !all_finite(eps_n, 6) || !all_finite(eps1, 6) || !all_finite(an, 6);
+    if (bad) {
+        for (int i = 0; i < 6; ++i) sigma[i] = a_out[i] = NAN;
+        if (tangent)
+            for (int i = 0; i < 36; ++i) tangent[i] = NAN;
+        return -1;
+    }
+    const phase_t *p = &ph[pid];
+    double C[6][6], K[6][6], de[6];
+    stiffness(p->E, p->nu, C);
+    hessian_omega_aa(p, C, K);
+    for (int i = 0; i < 6; ++i) de[i] = eps1[i] - eps_n[i];
+    const int tan = tangent != NULL;
+    double y[6], Y[36], k1[6], k2[6], k3[6], k4[6], yt[6], y1[6], yh[6];
+    double K1[36], K2[36], K3[36], K4[36], Yt[36], Y1[36], Yh[36], P2[6][6];
+    memcpy(y, an, sizeof y);
+    memset(Y, 0, sizeof Y);
+    rk_rhs(p, C, eps_n, de, 0.0, y, k1, tan ? P2 : NULL);
+    if (tan) rk_rhs_tan(P2, C, K, 0.0, Y, K1);
+    double s = 0.0, dt = h, fmax_ = 5.0;
+    int accepted = 0, attempts = 0, status = 0;
+    while (s < h) {
+        if (++attempts > max_steps) {
+            status = -1;
+            break;
+        }
+        const int last = dt >= h - s;
+        if (last) dt = h - s;
+        const double th0 = s / h, th2 = (s + 0.5 * dt) / h, th3 = (s + 0.75 * dt) / h;
+        const double th4 = last ? 1.0 : (s + dt) / h;
+        for (int i = 0; i < 6; ++i) yt[i] = y[i] + 0.5 * dt * k1[i];
+        rk_rhs(p, C, eps_n, de, th2, yt, k2, tan ? P2 : NULL);
+        if (tan) {
+            for (int i = 0; i < 36; ++i) Yt[i] = Y[i] + 0.5 * dt * K1[i];
+            rk_rhs_tan(P2, C, K, th2, Yt, K2);
+        }
+        for (int i = 0; i < 6; ++i) yt[i] = y[i] + 0.75 * dt * k2[i];
+        rk_rhs(p, C, eps_n, de, th3, yt, k3, tan ? P2 : NULL);
+        if (tan) {
+            for (int i = 0; i < 36; ++i) Yt[i] = Y[i] + 0.75 * dt * K2[i];
+            rk_rhs_tan(P2, C, K, th3, Yt, K3);
+        }
+        for (int i = 0; i < 6; ++i)
+            y1[i] = y[i] + dt * (2.0 / 9.0 * k1[i] + 1.0 / 3.0 * k2[i] + 4.0 / 9.0 * k3[i]);
+        rk_rhs(p, C, eps_n, de, th4, y1, k4, tan ? P2 : NULL);
+        if (tan) {
+            for (int i = 0; i < 36; ++i)
+                Y1[i] = Y[i] + dt * (2.0 / 9.0 * K1[i] + 1.0 / 3.0 * K2[i] + 4.0 / 9.0 * K3[i]);
+            rk_rhs_tan(P2, C, K, th4, Y1, K4);
+        }
+        for (int i = 0; i < 6; ++i)
+            yh[i] = y[i] + dt * (7.0 / 24.0 * k1[i] + 0.25 * k2[i] + 1.0 / 3.0 * k3[i] +
+                                 0.125 * k4[i]);
+        /* error measure on the stresses (and tangents) */
+        double e_s[6], e_1[6];
+        for (int i = 0; i < 6; ++i) {
+            e_s[i] = eps_n[i] + th0 * de[i];
+            e_1[i] = eps_n[i] + th4 * de[i];
+        }
+        double d0[6], d1[6], dh[6], z0[6], z1[6], zh[6];
+        for (int i = 0; i < 6; ++i) {
+            d0[i] = e_s[i] - y[i];
+            d1[i] = e_1[i] - y1[i];
+            dh[i] = e_1[i] - yh[i];
+        }
+        matvec(C, d0, z0);
+        matvec(C, d1, z1);
+        matvec(C, dh, zh);
+        double sum = 0.0;
+        int cnt = 6;
+        for (int i = 0; i < 6; ++i) {
+            const double r = (z1[i] - zh[i]) / rk_scale(atol, rtol, z0[i], z1[i]);
+            sum += r * r;
+        }
+        if (tan) {
+            for (int j = 0; j < 6; ++j)
+                for (int i = 0; i < 6; ++i) {
+                    /* T = C (theta I - Y): entry (i, j) */
+                    double t0 = th0 * C[i][j], t1 = th4 * C[i][j], tq = th4 * C[i][j];
+                    for (int q = 0; q < 6; ++q) {
+                        t0 -= C[i][q] * Y[q * 6 + j];
+                        t1 -= C[i][q] * Y1[q * 6 + j];
+                    }
+                    for (int q = 0; q < 6; ++q) {
+                        double yhq = Y[q * 6 + j] + dt * (7.0 / 24.0 * K1[q * 6 + j] +
+                                                           0.25 * K2[q * 6 + j] +
+                                                           1.0 / 3.0 * K3[q * 6 + j] +
+                                                           0.125 * K4[q * 6 + j]);
+                        Yh[q * 6 + j] = yhq;
+                        tq -= C[i][q] * yhq;
+                    }
+                    const double r = (t1 - tq) / rk_scale(atol, rtol, t0, t1);
+                    sum += r * r;
+                }
+            cnt += 36;
+        }
+        const double err = sqrt(sum / cnt);
+        double fac = err > 0.0 ? 0.9 * pow(err, -1.0 / 3.0) : fmax_;
+        fac = fmin(fmax_, fmax(0.2, fac));
+        if (err <= 1.0) {
+            ++accepted;
+            s = last ? h : s + dt;
+            memcpy(y, y1, sizeof y);
+            memcpy(k1, k4, sizeof k1);
+            if (tan) {
+                memcpy(Y, Y1, sizeof Y);
+                memcpy(K1, K4, sizeof K1);
+            }
+            dt *= fac;
+            fmax_ = 5.0;
+        } else {
+            ++*rejected;
+            dt *= fmin(1.0, fac);
+            fmax_ = 1.0;
+        }
+    }
+    (void)Yh;
+    double d[6];
+    for (int i = 0; i < 6; ++i) {
+        a_out[i] = y[i];
+        d[i] = eps1[i] - y[i];
+    }
+    matvec(C, d, sigma);
+    if (tangent)
+        for (int i = 0; i < 6; ++i)
+            for (int j = 0; j < 6; ++j) {
+                double t = C[i][j];
+                for (int q = 0; q < 6; ++q) t -= C[i][q] * Y[q * 6 + j];
+                tangent[i * 6 + j] = t;
+            }
+    return status < 0 ? -1 : accepted;
+}
+
+/* Adaptive ode23 evaluation of n points: eps_n, eps1, a_old [6][n]; sigma,
+ * a_out [6][n]; tangent [36][n] or NULL; steps, rejected [n] or NULL.
+ * Returns 0, or -1 on invalid arguments. */
+int oracle_evaluate_rk23(int64_t n, const double *eps_n, const double *eps1,
+                         const double *a_old, const uint8_t *phase, int n_phases,
+                         const double *par, double h, double atol, double rtol, int max_steps,
+                         double *sigma, double *a_out, double *tangent, int32_t *steps,
+                         int32_t *rejected)
+{
+    phase_t ph[256];
+    if (n < 0 || !eps_n || !eps1 || !a_old || !phase || !par || !sigma || !a_out) return -1;
+    if (!(h > 0.0) || !isfinite(h) || !(atol >= 0.0) || !(rtol > 0.0) || max_steps < 1)
+        return -1;
+    if (load_all(n_phases, par, ph) != 0) return -1;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        double e0[6], e1[6], an[6], s[6], ao[6], t[36];
+        for (int c = 0; c < 6; ++c) {
+            e0[c] = eps_n[c * n + i];
+            e1[c] = eps1[c * n + i];
+            an[c] = a_old[c * n + i];
+        }
+        int rej = 0;
+        int st = rk23_point(ph, n_phases, phase[i], e0, e1, an, h, atol, rtol, max_steps, s, ao,
+                            tangent ? t : NULL, &rej);
+        for (int c = 0; c < 6; ++c) {
+            sigma[c * n + i] = s[c];
+            a_out[c * n + i] = ao[c];
+        }
+        if (tangent)
+            for (int c = 0; c < 36; ++c) tangent[c * n + i] = t[c];
+        if (steps) steps[i] = st;
+        if (rejected) rejected[i] = rej;
+    }
+    return 0;
+}

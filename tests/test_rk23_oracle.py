@@ -1,0 +1,125 @@
+"""Pins of the oracle's adaptive Bogacki-Shampine 3(2) evaluation (CPU)."""
+import numpy as np
+
+import oracle
+from paper_2006_04391_amd import inputs
+from tests import _tensor as T
+
+ELASTIC = dict(kind=0, E=72000.0, nu=0.22, H=0.0, sigma_y=0.0, sigma0=1.0, eps0=0.0, n=1.0)
+
+
+def _vp(n_exp, **kw):
+    p = dict(kind=1, E=2500.0, nu=0.35, H=0.0, sigma_y=0.0, sigma0=50.0, eps0=1e-3, n=n_exp)
+    p.update(kw)
+    return p
+
+
+def _q(sig):
+    return np.array([T.mises(T.dev(T.stress_tensor(sig[:, i]))) for i in range(sig.shape[1])])
+
+
+def _relaxation_case(n_pts=6, e11=2e-2, seed=0):
+    rng = np.random.default_rng(seed)
+    eps = np.zeros((6, n_pts))
+    eps[0] = e11 * (1 + 0.1 * rng.random(n_pts))
+    eps[1:] = 1e-3 * rng.normal(size=(5, n_pts))
+    return eps, np.zeros((6, n_pts))
+
+
+def test_elastic_points_take_one_step():
+    rng = np.random.default_rng(1)
+    e0, e1 = rng.normal(size=(6, 5)) * 1e-3, rng.normal(size=(6, 5)) * 1e-3
+    an = rng.normal(size=(6, 5)) * 1e-4
+    r = oracle.evaluate_rk23(e0, e1, an, np.zeros(5, np.uint8), [ELASTIC], tangent=True)
+    assert np.all(r["steps"] == 1) and np.all(r["rejected"] == 0)
+    assert np.array_equal(r["a_out"], an)
+    for i in range(5):
+        sig = T.stress_voigt(T.hooke(ELASTIC["E"], ELASTIC["nu"], T.strain_tensor(e1[:, i] - an[:, i])))
+        np.testing.assert_allclose(r["sigma"][:, i], sig, rtol=1e-13, atol=1e-12)
+    C = np.array([T.stress_voigt(T.hooke(ELASTIC["E"], ELASTIC["nu"], T.strain_tensor(np.eye(6)[c])))
+                  for c in range(6)]).T
+    np.testing.assert_allclose(r["tangent"][:, 0].reshape(6, 6), C, rtol=1e-13)
+
+
+def test_linear_viscous_relaxation_is_exponential():
+    """n = 1, fixed strain: q(t) = q_0 exp(-3 mu eps0 t / sigma0)."""
+    p = _vp(1.0)
+    eps, a0 = _relaxation_case()
+    mu = T.lame(p["E"], p["nu"])[1]
+    h = 0.4
+    q0 = _q(oracle.evaluate(eps, a0, np.zeros(eps.shape[1], np.uint8), [p], h=1e-30)["sigma"])
+    exact = q0 * np.exp(-3 * mu * p["eps0"] * h / p["sigma0"])
+    tight = oracle.evaluate_rk23(eps, eps, a0, np.zeros(eps.shape[1], np.uint8), [p], h=h,
+                                 atol=1e-14, rtol=1e-11)
+    np.testing.assert_allclose(_q(tight["sigma"]), exact, rtol=1e-8)
+    loose = oracle.evaluate_rk23(eps, eps, a0, np.zeros(eps.shape[1], np.uint8), [p], h=h)
+    assert np.abs(_q(loose["sigma"]) / exact - 1).max() < 5e-3
+    assert loose["steps"].min() >= 1 and tight["steps"].min() > loose["steps"].max()
+
+
+def test_power_law_relaxation_matches_the_exact_solution():
+    """n = 5, fixed strain: q^(1-n)(t) = q_0^(1-n) + 3 mu eps0 (n-1) sigma0^-n t."""
+    p = _vp(5.0)
+    eps, a0 = _relaxation_case(e11=5e-2, seed=2)
+    mu = T.lame(p["E"], p["nu"])[1]
+    h = 0.3
+    ph = np.zeros(eps.shape[1], np.uint8)
+    q0 = _q(oracle.evaluate(eps, a0, ph, [p], h=1e-30)["sigma"])
+    n = p["n"]
+    exact = (q0 ** (1 - n) + 3 * mu * p["eps0"] * (n - 1) * p["sigma0"] ** (-n) * h) ** (1 / (1 - n))
+    r = oracle.evaluate_rk23(eps, eps, a0, ph, [p], h=h, atol=1e-14, rtol=1e-11)
+    np.testing.assert_allclose(_q(r["sigma"]), exact, rtol=1e-8)
+    # flow keeps the direction of the initial deviatoric stress (radial)
+    s0 = oracle.evaluate(eps, a0, ph, [p], h=1e-30)["sigma"]
+    for i in range(eps.shape[1]):
+        d = r["a_out"][:, i] - a0[:, i]
+        g = np.array([(2 * s0[0, i] - s0[1, i] - s0[2, i]) / 3, (2 * s0[1, i] - s0[0, i] - s0[2, i]) / 3,
+                      (2 * s0[2, i] - s0[0, i] - s0[1, i]) / 3, 2 * s0[3, i], 2 * s0[4, i], 2 * s0[5, i]])
+        np.testing.assert_allclose(d / np.linalg.norm(d), g / np.linalg.norm(g), atol=1e-10)
+
+
+def test_error_control_converges_with_the_tolerance():
+    """Strain ramp with the paper's parameters: the deviation from a tightly
+    integrated reference shrinks with the tolerance."""
+    ps = inputs.points_random(64, seed=3, phases=inputs.paper_phases(), e11=4e-3, std=5e-4,
+                              incl_frac=0.0)
+    e0 = np.zeros_like(ps.eps)
+    ref = oracle.evaluate_rk23(e0, ps.eps, ps.a_old, ps.phase, ps.phases, h=1.0, atol=1e-14,
+                               rtol=1e-12)["sigma"]
+    errs = []
+    for rtol in (1e-3, 1e-5, 1e-7):
+        s = oracle.evaluate_rk23(e0, ps.eps, ps.a_old, ps.phase, ps.phases, h=1.0, atol=1e-9,
+                                 rtol=rtol)["sigma"]
+        errs.append(np.abs(s - ref).max() / np.abs(ref).max())
+    assert errs[0] < 3e-3 and errs[1] < errs[0] / 20 and errs[2] < errs[1] / 20, errs
+
+
+def test_tangent_matches_central_differences():
+    ps = inputs.points_random(16, seed=4, phases=inputs.paper_phases(), e11=4e-3, std=5e-4,
+                              incl_frac=0.0)
+    e0 = np.zeros_like(ps.eps)
+    kw = dict(h=1.0, atol=1e-14, rtol=1e-12)
+    r = oracle.evaluate_rk23(e0, ps.eps, ps.a_old, ps.phase, ps.phases, tangent=True, **kw)
+    Ct = r["tangent"].reshape(6, 6, -1)
+    for c in range(6):
+        d = 1e-5 * np.abs(ps.eps).max()
+        ep, em = ps.eps.copy(), ps.eps.copy()
+        ep[c] += d
+        em[c] -= d
+        sp = oracle.evaluate_rk23(e0, ep, ps.a_old, ps.phase, ps.phases, **kw)["sigma"]
+        sm = oracle.evaluate_rk23(e0, em, ps.a_old, ps.phase, ps.phases, **kw)["sigma"]
+        fd = (sp - sm) / (2 * d)
+        np.testing.assert_allclose(Ct[:, c, :], fd, rtol=0, atol=1e-6 * np.abs(Ct).max())
+
+
+def test_invalid_points_and_step_limit():
+    p = _vp(5.0)
+    eps, a0 = _relaxation_case(n_pts=3, e11=5e-2)
+    eps[0, 1] = np.nan
+    ph = np.array([0, 0, 3], np.uint8)
+    r = oracle.evaluate_rk23(eps, eps, a0, ph, [p], h=0.3)
+    assert r["steps"][0] >= 1 and r["steps"][1] == -1 and r["steps"][2] == -1
+    assert np.all(np.isnan(r["sigma"][:, 1:]))
+    r = oracle.evaluate_rk23(eps[:, :1], eps[:, :1], a0[:, :1], ph[:1], [p], h=0.3, max_steps=1,
+                             rtol=1e-12, atol=1e-14)
+    assert r["steps"][0] == -1
