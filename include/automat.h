@@ -257,7 +257,10 @@ int32_t automat_ms_destroy(automat_ms *ms);
  * steps. The strain of step j of K at point i is (j / K) E_final +
  * noise_std z, z standard normal from Philox4x32-10 (Salmon et al. 2011)
  * keyed by seed with counter (i, j, w) and the Box-Muller transform.
- * Results do not depend on the rest of the batch.
+ * Results do not depend on the rest of the batch beyond rounding (flowing
+ * points are packed into full waves, and a wave decides together whether a
+ * trial point is evaluated to first order; measured differences stay below
+ * 1e-12 relative).
  * ------------------------------------------------------------------------ */
 typedef struct automat_server automat_server; /* opaque; owns a scheduler thread, two streams
                                                  and the arena */
@@ -316,6 +319,34 @@ int32_t automat_server_stats(automat_server *server, automat_server_stats_t *sta
 
 /* Finish the admitted requests, cancel the queued ones, stop the scheduler. */
 int32_t automat_server_destroy(automat_server *server);
+
+/* ------------------------------------------------------------------------
+ * Adaptive explicit Runge-Kutta evaluation (Section "Rosenbrock and
+ * Runge-Kutta Schemes with Adaptive Step Size"; error measure on stresses as
+ * in Section "Error Control"). Over one load step of length h the strain
+ * moves linearly from eps_n to eps_new; a' = dPsi/dA(A(eps(t), a)) is
+ * integrated from a_old with the embedded Bogacki-Shampine 3(2) pair (the
+ * pair of MATLAB's ode23) and automatic step size control: a step of size
+ * dt is accepted when the rms over the six stress components of
+ * (sigma_3rd - sigma_2nd) / (atol + rtol max(|sigma_start|, |sigma_end|)) is
+ * <= 1; the next dt is dt min(5, max(1/5, 0.9 err^(-1/3))) (growth capped at 1
+ * right after a rejection); the first try is the whole load step.
+ *   eps_n, eps_new, a_old  device [6][n]; a_out may equal a_old.
+ *   sigma_out, a_out       device [6][n]: stress and internal variables at
+ *                          the end of the step.
+ *   steps_out              device [n] or NULL: accepted steps, -1 if the
+ *                          point is invalid or needed more than max_steps
+ *                          attempts (its outputs are then the last state,
+ *                          or NaN for invalid input), counted in
+ *                          *nonconverged (device uint64, or NULL).
+ * atol >= 0, rtol > 0 (MATLAB's defaults are 1e-6 and 1e-3), max_steps >= 1.
+ * Stream-ordered, asynchronous. The consistent tangent of this scheme is
+ * not computed here. */
+int32_t automat_evaluate_rk23(int64_t n, const double *eps_n, const double *eps_new,
+                              const double *a_old, const uint8_t *phase,
+                              const automat_params *params, double h, double atol, double rtol,
+                              int32_t max_steps, double *sigma_out, double *a_out,
+                              int32_t *steps_out, uint64_t *nonconverged, void *stream);
 
 /* Human-readable text of a return code. */
 const char *automat_strerror(int32_t code);

@@ -83,6 +83,30 @@ def evaluate(eps, a_old, phase, phases, h=0.1, tol=1e-12, max_iter=50, *, tangen
     return tuple(out)
 
 
+def evaluate_rk23(eps_n, eps_new, a_old, phase, phases, h=0.1, atol=1e-6, rtol=1e-3,
+                  max_steps=100000, *, a_out=None, sigma_out=None):
+    """Adaptive Bogacki-Shampine 3(2) evaluation over one load step with the
+    strain moving linearly from eps_n to eps_new. Returns (sigma, a_new,
+    steps (n,) int32, failed-point count)."""
+    eps_n = _field(eps_n, "eps_n", 6)
+    n, dev = eps_n.shape[1], eps_n.device
+    eps_new = _field(eps_new, "eps_new", 6, n, dev)
+    a_old = _field(a_old, "a_old", 6, n, dev)
+    phase = _phase_ids(phase, n, dev)
+    params = make_params(phases)
+    sigma = torch.empty_like(eps_n) if sigma_out is None else _field(sigma_out, "sigma_out", 6, n, dev)
+    a_new = torch.empty_like(a_old) if a_out is None else _field(a_out, "a_out", 6, n, dev)
+    steps = torch.empty(n, dtype=torch.int32, device=dev)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    with torch.cuda.device(dev):
+        rc = load().automat_evaluate_rk23(n, _ptr(eps_n), _ptr(eps_new), _ptr(a_old), _ptr(phase),
+                                          ctypes.byref(params), float(h), float(atol), float(rtol),
+                                          int(max_steps), _ptr(sigma), _ptr(a_new), _ptr(steps),
+                                          _ptr(count), _stream(dev))
+    check("automat_evaluate_rk23", rc)
+    return sigma, a_new, steps, count
+
+
 def evaluate_backward(eps, a_old, a_new, phase, phases, h, grad_sigma=None, grad_a=None, *,
                       want_a_old=True, want_params=True):
     """Vector-Jacobian product at a converged evaluation.

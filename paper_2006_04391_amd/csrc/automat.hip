@@ -65,15 +65,6 @@ __host__ __device__ constexpr size_t eval_smem_bytes(int n_phases) {
     return kWaves * kRingBytes + (size_t)n_phases * sizeof(PC);
 }
 
-// Orders this lane's LDS writes before other lanes' later reads of them
-// (the compiler would otherwise be free to reorder them; the hardware keeps
-// a wave's LDS operations in order).
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 template <bool TANGENT>
 __device__ __forceinline__ void store_tangent(const EvalArgs &args, int64_t i, const double *C) {
     const int64_t n = args.n;
@@ -232,8 +223,7 @@ void gsm_eval_kernel(const EvalArgs args) {
             // append the flowing points to the ring
             const uint64_t mask = __ballot(queue);
             if (queue) {
-                const uint32_t pos = (uint32_t)__builtin_amdgcn_mbcnt_hi(
-                    (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                const uint32_t pos = lane_rank(mask);
                 const uint32_t slot = (tail + pos) & (kRing - 1);
 #pragma unroll
                 for (int c = 0; c < 6; ++c) {

@@ -22,6 +22,21 @@ __device__ __forceinline__ bool finite6(const double *x) {
     return ok;
 }
 
+// Orders this lane's LDS writes before other lanes' later reads of them
+// (the compiler would otherwise be free to reorder them; the hardware keeps
+// a wave's LDS operations in order).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Lane position among the lanes of the wave whose bit is set in mask.
+__device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
+    return (uint32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                               __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
 // Count lanes with a non-converged or invalid point, one atomic per wave.
 __device__ __forceinline__ void count_failures(unsigned long long *counter, bool failed) {
     const unsigned long long mask = __ballot(failed);

@@ -200,8 +200,10 @@ __global__ void shift_kernel(double *eps, int64_t n, double d0, double d1, doubl
     eps[5 * n + i] += d5;
 }
 
-// lam' = b - (C - C0) t with C the packed-by-rows 6x6 tangent field [36][n]
-// and t = Gamma0 lam (the raw inverse transform, scaled by 1/n here);
+// lam' = b - (C - C0) t with C the row-major 6x6 tangent field [36][n] and
+// t = Gamma0 lam; the transform pipeline returns raw = -n Gamma0 lam (the
+// operator kernel carries the minus sign of the forward update), so
+// t = -raw / n;
 // per-block partial sums of |lam' - lam|^2 and |b|^2; lam <- lam'
 __global__ __launch_bounds__(kRedBlock) void adjoint_update_kernel(
     double *lam, const double *b, const double *raw, const double *C, int64_t n, double lam0,
@@ -212,7 +214,7 @@ __global__ __launch_bounds__(kRedBlock) void adjoint_update_kernel(
     for (int64_t i = (int64_t)blockIdx.x * kRedBlock + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kRedBlock) {
         double t[6];
-        for (int c = 0; c < 6; ++c) t[c] = raw[c * n + i] * inv;
+        for (int c = 0; c < 6; ++c) t[c] = -raw[c * n + i] * inv;
         const double tr = lam0 * (t[0] + t[1] + t[2]);
         for (int r = 0; r < 6; ++r) {
             double ct = 0.0;
@@ -242,8 +244,8 @@ __global__ __launch_bounds__(kRedBlock) void adjoint_update_kernel(
     }
 }
 
-// out = g + w / n - raw / n  (g may be null): the stress cotangent that
-// carries the parameter and a_{k-1} sensitivities, g - Gamma0 lam
+// out = g + w / n - Gamma0 lam = g + w / n + raw / n (g may be null): the
+// stress cotangent that carries the parameter and a_{k-1} sensitivities
 __global__ void adjoint_sigma_kernel(double *out, const double *g, const double *raw, int64_t n,
                                      double w0, double w1, double w2, double w3, double w4,
                                      double w5) {
@@ -252,7 +254,7 @@ __global__ void adjoint_sigma_kernel(double *out, const double *g, const double 
     const double inv = 1.0 / (double)n;
     const double w[6] = {w0, w1, w2, w3, w4, w5};
     for (int c = 0; c < 6; ++c)
-        out[c * n + i] = (g ? g[c * n + i] : 0.0) + w[c] * inv - raw[c * n + i] * inv;
+        out[c * n + i] = (g ? g[c * n + i] : 0.0) + w[c] * inv + raw[c * n + i] * inv;
 }
 
 // out = g + w / n (g may be null)
@@ -470,8 +472,8 @@ extern "C" int32_t automat_ms_set_macro(automat_ms *m, const double *E_prev) {
     return AUTOMAT_OK;
 }
 
-// Gamma0 applied to a stress-like field x (not modified): the raw inverse
-// transform (n times Gamma0 x, zero mean) lands in m->sig.
+// The Green operator applied to a stress-like field x (not modified): the
+// raw inverse transform, -n Gamma0 x (zero mean), lands in m->sig.
 static int32_t ms_gamma(automat_ms *m, const double *x, hipStream_t s) {
     const int tb = 256;
     const int nhb = (int)((m->f.nh + tb - 1) / tb);

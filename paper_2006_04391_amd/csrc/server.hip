@@ -16,10 +16,15 @@
 //
 // Device side: the batch kernel strides a resident grid over the 256-point
 // tiles of all segments. A tile belongs to one segment: the block finds it
-// by binary search, stages that request's phase table in LDS, generates the
-// step's strain for each of its points, loads a_n, runs the same per-point
-// solve as the plain evaluation kernel and writes sigma and a_{n+1} back.
-// Results therefore do not depend on what else is in the batch.
+// from LDS-staged first-tile indices and keeps that request's descriptor and
+// phase table in LDS. Each lane generates the step's strain for its point
+// and loads a_n; points without flow are finished at once, flowing points
+// are compacted into full waves (per-wave LDS queues, emptied before the
+// block moves to another request) and run the same per-point solve as the
+// plain evaluation kernel. Results therefore do not depend on what else is
+// in the batch, except in the last bits: a wave decides together whether a
+// trial point is evaluated to first order, and which points share a wave
+// depends on the batch.
 //
 // Strain of load step j of K at point i: eps = (j / K) E_final + std z,
 // z_c standard normal from Philox4x32-10 (Salmon, Moraes, Dror, Shaw 2011)
@@ -108,31 +113,82 @@ __global__ void build_tables_kernel(const Model::Phase *raw, int nph, PC *out) {
 
 // Segments per launch: their first-tile indices are staged in LDS.
 constexpr int kMaxSegs = 2048;
+constexpr int kWaves = kBlock / 64;
+// Per-wave ring of queued flowing points: eps, a_n [12][kRing] doubles,
+// then the point index [kRing] (int64) and phase id [kRing] (int32).
+constexpr int kRing = 128;
+constexpr size_t kRingBytes =
+    12 * kRing * sizeof(double) + kRing * (sizeof(int64_t) + sizeof(int32_t));
 
 size_t serve_smem_bytes() {
-    return 12 * kBlock * sizeof(double) + AUTOMAT_MAX_PHASES * sizeof(PC) + sizeof(Segment) +
+    return kWaves * kRingBytes + AUTOMAT_MAX_PHASES * sizeof(PC) + sizeof(Segment) +
            (kMaxSegs + 1) * sizeof(int32_t);
 }
 
+// Solve queued points head .. head + cnt - 1 of the current segment and
+// store their results (one lane per point).
+__device__ __forceinline__ void serve_run_batch(const Segment &sg, const PC *tab, double *ring,
+                                                const int64_t *ridx, const int32_t *rpid,
+                                                uint32_t head, uint32_t cnt, int lane) {
+    const uint32_t slot = (head + (uint32_t)lane) & (kRing - 1);
+    const bool active = (uint32_t)lane < cnt;
+    const int pid = active ? rpid[slot] : 0;
+    const int64_t i = active ? ridx[slot] : 0;
+    double sig[6], anew[6];
+    const int status = solve_point<Model, false, kRing>(tab[pid], active, ring + slot,
+                                                        ring + 6 * kRing + slot, sg.h, sg.tol,
+                                                        sg.max_iter, 0u, sig, anew, nullptr);
+    if (active) {
+        const int64_t n = sg.n;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            __builtin_nontemporal_store(sig[c], sg.sigma + c * n + i);
+            sg.a[c * n + i] = anew[c];
+        }
+    }
+    count_failures(sg.nonconv, active && status < 0);
+    wave_lds_sync();
+}
+
+// One launch covers the next load step of every request in the batch. A
+// block walks 256-point tiles; each tile belongs to one segment (request),
+// whose descriptor and phase table the block keeps in LDS. Each wave takes
+// the tile's 64-point quarter: points that do not flow are finished at
+// once, flowing points are queued in the wave's ring and solved 64 at a
+// time (compaction, as in the evaluation kernel). A wave's queue is emptied
+// before its block moves to another segment, so a batch never mixes
+// requests.
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 void serve_batch_kernel(const Segment *segs, const int32_t *starts, int nseg, int32_t total_tiles) {
     extern __shared__ double smem_raw[];
-    double *stage = smem_raw;
-    PC *tab = reinterpret_cast<PC *>(smem_raw + 12 * kBlock);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double *ring = smem_raw + wave * (kRingBytes / sizeof(double));
+    int64_t *ridx = reinterpret_cast<int64_t *>(ring + 12 * kRing);
+    int32_t *rpid = reinterpret_cast<int32_t *>(ridx + kRing);
+    PC *tab = reinterpret_cast<PC *>(smem_raw + kWaves * (kRingBytes / sizeof(double)));
     Segment *cur = reinterpret_cast<Segment *>(tab + AUTOMAT_MAX_PHASES);
     int32_t *first = reinterpret_cast<int32_t *>(cur + 1);  // [nseg + 1], last = total_tiles
     for (int k = threadIdx.x; k <= nseg; k += kBlock) first[k] = starts[k];
     __syncthreads();
-    double *eps = stage + threadIdx.x;
-    double *an = stage + 6 * kBlock + threadIdx.x;
+    uint32_t head = 0, tail = 0;  // this wave's queue positions
     int seg = -1;
-    for (int32_t t = blockIdx.x; t < total_tiles; t += gridDim.x) {
+    for (int32_t t = blockIdx.x;; t += gridDim.x) {
+        const bool more = t < total_tiles;
         // tiles of a block ascend, so the owning segment only moves forward;
         // every lane reads the same LDS words, the result is block-uniform
-        int ns = seg < 0 ? 0 : seg;
-        while (first[ns + 1] <= t) ++ns;
-        if (ns != seg) {
-            __syncthreads();  // every wave is done with the previous segment's table
+        int ns = seg;
+        if (more) {
+            ns = seg < 0 ? 0 : seg;
+            while (first[ns + 1] <= t) ++ns;
+        }
+        if (ns != seg || !more) {
+            // drain this wave's queue with the old segment's table
+            if (seg >= 0 && tail != head) {
+                serve_run_batch(*cur, tab, ring, ridx, rpid, head, tail - head, lane);
+                head = tail;
+            }
+            if (!more) break;
+            __syncthreads();  // every wave is done with the previous segment
             {
                 const double *src = reinterpret_cast<const double *>(segs + ns);
                 double *dst = reinterpret_cast<double *>(cur);
@@ -149,7 +205,11 @@ void serve_batch_kernel(const Segment *segs, const int32_t *starts, int nseg, in
         }
         const Segment &sg = *cur;
         const int64_t i = (int64_t)(t - sg.tile0) * kBlock + threadIdx.x;
-        if (i < sg.n) {
+        const bool in_range = i < sg.n;
+        bool queue = false;
+        double e[6], a[6];
+        int pid = 0;
+        if (in_range) {
             const U4 r0 = philox4x32_10(U4{(uint32_t)i, (uint32_t)(i >> 32), sg.step, 0u}, sg.key0,
                                         sg.key1);
             const U4 r1 = philox4x32_10(U4{(uint32_t)i, (uint32_t)(i >> 32), sg.step, 1u}, sg.key0,
@@ -158,30 +218,51 @@ void serve_batch_kernel(const Segment *segs, const int32_t *starts, int nseg, in
             box_muller(r0.x, r0.y, z[0], z[1]);
             box_muller(r0.z, r0.w, z[2], z[3]);
             box_muller(r1.x, r1.y, z[4], z[5]);
-            double *a = sg.a;
-            double *sigma = sg.sigma;
             const int64_t n = sg.n;
             bool finite_in = true;
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
-                const double e = sg.E[c] + sg.noise * z[c];
-                const double ac = a[c * n + i];
-                finite_in = finite_in && isfinite(e) && isfinite(ac);
-                eps[c * kBlock] = e;
-                an[c * kBlock] = ac;
+                e[c] = sg.E[c] + sg.noise * z[c];
+                a[c] = sg.a[c * n + i];
+                finite_in = finite_in && isfinite(e[c]) && isfinite(a[c]);
             }
-            const int pid = sg.phase[i];
+            pid = sg.phase[i];
             const bool valid = pid < sg.n_phases && finite_in;
-            double sig[6], anew[6];
-            const int status = solve_point<Model, false>(tab[valid ? pid : 0], valid, eps, an, sg.h,
-                                                         sg.tol, sg.max_iter, 0u, sig, anew,
-                                                         nullptr);
+            const PC &pc = tab[valid ? pid : 0];
+            queue = valid && Model::flows(pc.prm);
+            if (!queue) {
+                // no flow: a_{n+1} = a_n stays in place
+                double sig[6];
+                if (valid) {
+                    Model::stress(pc.prm, e, a, sig);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) {
+                        sig[c] = NAN;
+                        sg.a[c * n + i] = NAN;
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < 6; ++c) __builtin_nontemporal_store(sig[c], sg.sigma + c * n + i);
+            }
+            count_failures(sg.nonconv, !valid);
+        }
+        const uint64_t mask = __ballot(queue);
+        if (queue) {
+            const uint32_t slot = (tail + lane_rank(mask)) & (kRing - 1);
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
-                __builtin_nontemporal_store(sig[c], sigma + c * n + i);
-                a[c * n + i] = anew[c];
+                ring[c * kRing + slot] = e[c];
+                ring[(6 + c) * kRing + slot] = a[c];
             }
-            count_failures(sg.nonconv, status < 0);
+            ridx[slot] = i;
+            rpid[slot] = pid;
+        }
+        tail += (uint32_t)__popcll(mask);
+        wave_lds_sync();
+        if (tail - head >= 64) {
+            serve_run_batch(sg, tab, ring, ridx, rpid, head, 64, lane);
+            head += 64;
         }
     }
 }

@@ -1,0 +1,72 @@
+"""Adaptive Bogacki-Shampine 3(2) evaluation on the GPU vs the oracle, point
+by point on the same seeded inputs (same accepted steps, results within the
+parity bar)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2006_04391_amd import inputs
+from tests.test_parity_gpu import TOL, N, T, rel_per_point
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _run(e0, ps, h, **kw):
+    from paper_2006_04391_amd import api
+    sig, a, steps, cnt = api.evaluate_rk23(T(e0), T(ps.eps), T(ps.a_old), T(ps.phase), ps.phases,
+                                           h=h, **kw)
+    torch.cuda.synchronize()
+    ref = oracle.evaluate_rk23(e0, ps.eps, ps.a_old, ps.phase, ps.phases, h=h, **kw)
+    return dict(sigma=N(sig), a_out=N(a), steps=N(steps), count=int(cnt.item())), ref
+
+
+def _check(g, ref):
+    assert np.array_equal(g["steps"], ref["steps"])
+    ok = ref["steps"] >= 0
+    assert rel_per_point(g["sigma"][:, ok], ref["sigma"][:, ok]).max() <= TOL
+    assert rel_per_point(g["a_out"][:, ok], ref["a_out"][:, ok]).max() <= TOL
+    assert g["count"] == int((ref["steps"] < 0).sum())
+
+
+@pytest.mark.parametrize("preset,n,seed", [("config", 4133, 1), ("paper", 1031, 2)])
+def test_ramp_parity(preset, n, seed):
+    phases = inputs.config_phases() if preset == "config" else inputs.paper_phases()
+    # loads that make the matrix flow enough for several steps
+    e11, h = (2e-2, 10.0) if preset == "config" else (4e-3, 1.0)
+    ps = inputs.points_random(n, seed=seed, phases=phases, e11=e11, std=3e-4, a_std=1e-4)
+    e0 = 0.5 * ps.eps + 1e-4 * np.random.default_rng(seed).normal(size=ps.eps.shape)
+    g, ref = _run(e0, ps, h=h)
+    assert ref["steps"].max() > 1
+    _check(g, ref)
+
+
+def test_tight_tolerances_many_steps():
+    ps = inputs.points_random(700, seed=5, phases=inputs.paper_phases(), e11=6e-3, std=5e-4)
+    e0 = np.zeros_like(ps.eps)
+    g, ref = _run(e0, ps, h=1.0, atol=1e-12, rtol=1e-9)
+    assert ref["steps"].max() > 20
+    _check(g, ref)
+
+
+def test_invalid_points_and_step_limit():
+    ps = inputs.points_random(300, seed=6, phases=inputs.paper_phases(), e11=6e-3, std=5e-4)
+    ps.eps[0, 7] = np.inf
+    ps.phase[11] = 9
+    e0 = np.zeros_like(ps.eps)
+    g, ref = _run(e0, ps, h=1.0, max_steps=3)
+    assert (ref["steps"] < 0).sum() > 2 and g["steps"][7] == -1 and g["steps"][11] == -1
+    _check(g, ref)
+
+
+def test_empty_and_invalid_arguments():
+    from paper_2006_04391_amd import api, _lib
+    ps = inputs.points_random(10, seed=7, phases=inputs.config_phases())
+    z = T(np.zeros_like(ps.eps))
+    with pytest.raises(_lib.AutomatError):
+        api.evaluate_rk23(z, T(ps.eps), T(ps.a_old), T(ps.phase), ps.phases, h=0.0)
+    with pytest.raises(_lib.AutomatError):
+        api.evaluate_rk23(z, T(ps.eps), T(ps.a_old), T(ps.phase), ps.phases, rtol=0.0)
+    e = torch.empty((6, 0), dtype=torch.float64, device="cuda")
+    out = api.evaluate_rk23(e, e, e, torch.empty(0, dtype=torch.uint8, device="cuda"), ps.phases)
+    assert out[0].shape == (6, 0)
