@@ -365,7 +365,10 @@ extern "C" int32_t automat_evaluate_ex(int64_t n, const double *eps_new, const d
     rc = device_info(dev);
     if (rc) return rc;
     const int64_t tiles = (n + kBlock - 1) / kBlock;
-    const int64_t cap = (int64_t)dev.cus * (tangent_out ? dev.blocks_tan : dev.blocks_fwd);
+    // Two (tangent: four) rounds of resident blocks: blocks that finish
+    // early are replaced by the dispatcher, which evens out the end of the
+    // launch (two waves share a SIMD and one of them gets issue priority).
+    const int64_t cap = (int64_t)dev.cus * (tangent_out ? 4 * dev.blocks_tan : 2 * dev.blocks_fwd);
     const int grid = (int)(tiles < cap ? tiles : cap);
     const size_t smem = eval_smem_bytes(args.n_phases);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
