@@ -40,9 +40,19 @@ struct EvalArgs {
     int32_t max_iter;
     uint32_t flags;
     int32_t n_phases;
-    int32_t reserved;
+    int32_t polarize;  // nonzero: sigma_out receives sigma - C0 eps (basic scheme)
+    double lam0, mu0;  // isotropic reference medium C0 for polarize
     Model::Phase phases[AUTOMAT_MAX_PHASES];
 };
+
+// sig <- sig - C0 eps for an isotropic C0 (engineering shears)
+__device__ __forceinline__ void polarize6(double *sig, const double *e, double lam0, double mu0) {
+    const double tr = lam0 * (e[0] + e[1] + e[2]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) sig[c] -= tr + 2.0 * mu0 * e[c];
+#pragma unroll
+    for (int c = 3; c < 6; ++c) sig[c] -= mu0 * e[c];
+}
 
 #ifndef AUTOMAT_EVAL_WAVES
 #define AUTOMAT_EVAL_WAVES 2
@@ -93,6 +103,12 @@ __device__ __forceinline__ void run_batch(const EvalArgs &args, const PC *tab, d
                                                           args.max_iter, args.flags, sig, anew, C);
     if (active) {
         const int64_t n = args.n;
+        if (args.polarize) {
+            double e[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) e[c] = ring[c * kRing + slot];
+            polarize6(sig, e, args.lam0, args.mu0);
+        }
 #pragma unroll
         for (int c = 0; c < 6; ++c) __builtin_nontemporal_store(sig[c], args.sigma + c * n + i);
         if (args.a_out) {
@@ -199,6 +215,7 @@ void gsm_eval_kernel(const EvalArgs args) {
                 double sig[6];
                 if (valid) {
                     Model::stress(pc.prm, e, a, sig);
+                    if (args.polarize) polarize6(sig, e, args.lam0, args.mu0);
                 } else {
 #pragma unroll
                     for (int c = 0; c < 6; ++c) sig[c] = a[c] = NAN;
@@ -332,11 +349,37 @@ int32_t copy_params(const automat_params *params, Model::Phase *dst, int32_t *n_
 
 using namespace automat;
 
+static int32_t launch_evaluate(int64_t n, const double *eps_new, const double *a_old,
+                               const uint8_t *phase, const automat_params *params, double h,
+                               double tol, int32_t max_iter, double *sigma_out, double *a_out,
+                               double *tangent_out, int32_t *iters_out, uint64_t *nonconverged,
+                               uint32_t flags, const double *pol, void *stream);
+
 extern "C" int32_t automat_evaluate_ex(int64_t n, const double *eps_new, const double *a_old,
                                        const uint8_t *phase, const automat_params *params,
                                        double h, double tol, int32_t max_iter, double *sigma_out,
                                        double *a_out, double *tangent_out, int32_t *iters_out,
                                        uint64_t *nonconverged, uint32_t flags, void *stream) {
+    return launch_evaluate(n, eps_new, a_old, phase, params, h, tol, max_iter, sigma_out, a_out,
+                           tangent_out, iters_out, nonconverged, flags, nullptr, stream);
+}
+
+namespace automat {
+int32_t evaluate_polarized(int64_t n, const double *eps, const double *a_old,
+                           const uint8_t *phase, const automat_params *params, double h,
+                           double tol, int32_t max_iter, double lam0, double mu0, double *tau_out,
+                           void *stream) {
+    const double pol[2] = {lam0, mu0};
+    return launch_evaluate(n, eps, a_old, phase, params, h, tol, max_iter, tau_out, nullptr,
+                           nullptr, nullptr, nullptr, 0u, pol, stream);
+}
+}  // namespace automat
+
+static int32_t launch_evaluate(int64_t n, const double *eps_new, const double *a_old,
+                               const uint8_t *phase, const automat_params *params, double h,
+                               double tol, int32_t max_iter, double *sigma_out, double *a_out,
+                               double *tangent_out, int32_t *iters_out, uint64_t *nonconverged,
+                               uint32_t flags, const double *pol, void *stream) {
     if (n < 0) return AUTOMAT_EINVAL;
     if (!std::isfinite(h) || !(h > 0.0) || !std::isfinite(tol) || !(tol > 0.0) || max_iter < 1)
         return AUTOMAT_EINVAL;
@@ -360,6 +403,11 @@ extern "C" int32_t automat_evaluate_ex(int64_t n, const double *eps_new, const d
     args.tol = tol;
     args.max_iter = max_iter;
     args.flags = flags;
+    if (pol) {
+        args.polarize = 1;
+        args.lam0 = pol[0];
+        args.mu0 = pol[1];
+    }
 
     DeviceInfo dev;
     rc = device_info(dev);

@@ -13,6 +13,14 @@ namespace automat {
 // Validate an automat_params table and convert it to the kernels' layout.
 int32_t copy_params(const automat_params *params, MSGSM::Phase *dst, int32_t *n_phases);
 
+// One evaluation sweep that writes the polarization tau = sigma - C0 eps
+// (isotropic C0 = (lam0, mu0)) instead of sigma, for the basic scheme; no
+// a_{n+1}, tangent or iteration output.
+int32_t evaluate_polarized(int64_t n, const double *eps, const double *a_old,
+                           const uint8_t *phase, const automat_params *params, double h,
+                           double tol, int32_t max_iter, double lam0, double mu0, double *tau_out,
+                           void *stream);
+
 // Compute-unit count of the current device (cached per device).
 int32_t device_cus(int *cus);
 

@@ -7,8 +7,8 @@
 // with macroscopic strain E per step. With an isotropic reference medium
 // C0 = (lambda0, mu0), one iteration is
 //
-//   sigma   = material(eps, a_n)                       (automat kernels)
-//   tau     = sigma - C0 eps                           (polarization)
+//   tau     = material(eps, a_n) - C0 eps              (one evaluation sweep
+//                                                       writing the polarization)
 //   tau^    = FFT(tau)                                 (6 batched D2Z)
 //   eps^(xi)= -Gamma0(xi) : tau^(xi), xi != 0;  eps^(0) = E
 //   eps'    = IFFT(eps^) / N                           (6 batched Z2D)
@@ -44,21 +44,6 @@ struct MsField {
     int64_t n;   // real points
     int64_t nh;  // half-spectrum points nz * ny * (nx / 2 + 1)
 };
-
-// tau = sigma - C0 eps (in place in sigma), isotropic C0, engineering shears
-__global__ void polarize_kernel(double *sig, const double *eps, int64_t n, double lam0,
-                                double mu0) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double e0 = eps[i], e1 = eps[n + i], e2 = eps[2 * n + i];
-    const double tr = lam0 * (e0 + e1 + e2);
-    sig[i] -= tr + 2.0 * mu0 * e0;
-    sig[n + i] -= tr + 2.0 * mu0 * e1;
-    sig[2 * n + i] -= tr + 2.0 * mu0 * e2;
-    sig[3 * n + i] -= mu0 * eps[3 * n + i];
-    sig[4 * n + i] -= mu0 * eps[4 * n + i];
-    sig[5 * n + i] -= mu0 * eps[5 * n + i];
-}
 
 __device__ __forceinline__ double freq(int k, int N) { return (double)(k <= N / 2 ? k : k - N) / N; }
 
@@ -179,12 +164,21 @@ __global__ __launch_bounds__(kRedBlock) void mean6_kernel(const double *x, int64
     }
 }
 
-// fixed-order sum of m partials per row, rows = gridDim.x
-__global__ void finish_kernel(const double *partial, int m, double *out) {
-    if (threadIdx.x != 0) return;
+// sum of m partials per row (rows = gridDim.x, 256 threads per row) in a
+// fixed order: strided per-thread sums, then a tree over the threads, so the
+// result does not depend on timing
+__global__ __launch_bounds__(kRedBlock) void finish_kernel(const double *partial, int m,
+                                                           double *out) {
+    __shared__ double red[kRedBlock];
     double s = 0.0;
-    for (int b = 0; b < m; ++b) s += partial[blockIdx.x * m + b];
-    out[blockIdx.x] = s;
+    for (int b = threadIdx.x; b < m; b += kRedBlock) s += partial[blockIdx.x * m + b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kRedBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
 // eps += dE (uniform shift of the strain field)
@@ -414,19 +408,17 @@ extern "C" int32_t automat_ms_step(automat_ms *m, const uint8_t *phase, const do
     double err = 0.0;
     int32_t rc = AUTOMAT_OK;
     for (it = 1; it <= m->opts.max_iter; ++it) {
-        rc = automat_evaluate_ex(n, eps, a, phase, &m->params, h, m->opts.newton_tol,
-                                 m->opts.newton_max_iter, m->sig, nullptr, nullptr, nullptr,
-                                 nullptr, 0u, stream);
+        // material sweep writing the polarization tau = sigma - C0 eps
+        rc = evaluate_polarized(n, eps, a, phase, &m->params, h, m->opts.newton_tol,
+                                m->opts.newton_max_iter, m->lam0, m->mu0, m->sig, stream);
         if (rc) return rc;
-        hipLaunchKernelGGL(polarize_kernel, dim3(gb), dim3(tb), 0, s, m->sig, eps, n, m->lam0,
-                           m->mu0);
         if (hipfftExecD2Z(m->fwd, m->sig, m->spec) != HIPFFT_SUCCESS) return AUTOMAT_EHIP;
         hipLaunchKernelGGL(gamma_kernel, dim3(nhb), dim3(tb), 0, s, m->spec, m->f, c1, c2,
                            E_macro[0], E_macro[1], E_macro[2], E_macro[3], E_macro[4], E_macro[5]);
         if (hipfftExecZ2D(m->inv, m->spec, m->sig) != HIPFFT_SUCCESS) return AUTOMAT_EHIP;
         hipLaunchKernelGGL(update_kernel, dim3(rb), dim3(kRedBlock), 0, s, eps, m->sig, n,
                            m->partial);
-        hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(64), 0, s, m->partial, rb, m->scal);
+        hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedBlock), 0, s, m->partial, rb, m->scal);
         if (!m->opts.fixed_iter) {
             if (hipMemcpyAsync(m->host_scal, m->scal, sizeof(double), hipMemcpyDeviceToHost, s) !=
                     hipSuccess ||
@@ -452,7 +444,7 @@ extern "C" int32_t automat_ms_step(automat_ms *m, const uint8_t *phase, const do
     if (rc) return rc;
     if (sigma_mean) {
         hipLaunchKernelGGL(mean6_kernel, dim3(rb), dim3(kRedBlock), 0, s, sig, n, m->partial);
-        hipLaunchKernelGGL(finish_kernel, dim3(6), dim3(64), 0, s, m->partial, rb, m->scal);
+        hipLaunchKernelGGL(finish_kernel, dim3(6), dim3(kRedBlock), 0, s, m->partial, rb, m->scal);
         if (hipMemcpyAsync(m->host_scal, m->scal, 6 * sizeof(double), hipMemcpyDeviceToHost, s) !=
                 hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
@@ -542,7 +534,7 @@ extern "C" int32_t automat_ms_adjoint_step(automat_ms *m, const uint8_t *phase, 
         if (rc) return rc;
         hipLaunchKernelGGL(adjoint_update_kernel, dim3(rb), dim3(kRedBlock), 0, s, m->lam, m->rhs,
                            m->sig, m->tan, n, m->lam0, m->mu0, m->partial);
-        hipLaunchKernelGGL(finish_kernel, dim3(2), dim3(64), 0, s, m->partial, rb, m->scal);
+        hipLaunchKernelGGL(finish_kernel, dim3(2), dim3(kRedBlock), 0, s, m->partial, rb, m->scal);
         if (!m->opts.fixed_iter || it == m->opts.max_iter) {
             if (hipMemcpyAsync(m->host_scal, m->scal, 2 * sizeof(double), hipMemcpyDeviceToHost,
                                s) != hipSuccess ||
@@ -555,7 +547,7 @@ extern "C" int32_t automat_ms_adjoint_step(automat_ms *m, const uint8_t *phase, 
     if (it > m->opts.max_iter) it = m->opts.max_iter;
     // dL/dE = sum_x lam(x)
     hipLaunchKernelGGL(mean6_kernel, dim3(rb), dim3(kRedBlock), 0, s, m->lam, n, m->partial);
-    hipLaunchKernelGGL(finish_kernel, dim3(6), dim3(64), 0, s, m->partial, rb, m->scal);
+    hipLaunchKernelGGL(finish_kernel, dim3(6), dim3(kRedBlock), 0, s, m->partial, rb, m->scal);
     if (hipMemcpyAsync(m->host_scal, m->scal, 6 * sizeof(double), hipMemcpyDeviceToHost, s) !=
             hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
