@@ -36,10 +36,10 @@ BYTES_PER_POINT_TANGENT = BYTES_PER_POINT + 36 * 8            # 481
 # FETCH_SIZE / WRITE_SIZE (scaled by a 1 GiB copy calibration), keyed by the
 # hash of the kernel sources they were taken on; a changed kernel reports
 # traffic null until it is measured again.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {"99fad3151dd2637f": 3.483e9}
 # Executed FP64 FLOP per point of the forward kernel on the 256^3 batch
 # (rocprofv3 SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes / points), same keying.
-MEASURED_FP64_FLOP_PER_POINT = {}
+MEASURED_FP64_FLOP_PER_POINT = {"99fad3151dd2637f": 1428.0}
 KERNEL_SOURCES = ["automat.hip", "ad.hpp", "fastmath.hpp", "linalg6.hpp", "msgsm.hpp",
                   "gsm_point.hpp", "gsm_kernel.hpp"]
 
@@ -155,6 +155,7 @@ def main():
                     help="host processes generating the requests' microstructures")
     ap.add_argument("--ms-steps", type=int, default=20,
                     help="load steps of the 128^3 Moulinec-Suquet run (0 skips it)")
+    ap.add_argument("--no-rk23", action="store_true", help="skip the adaptive ode23 leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (known traffic: 1 GiB read, "
                          "1 GiB written) so profiler byte counters can be scaled")
@@ -258,6 +259,28 @@ def main():
         out["tangent"] = {"ms_per_step": ms_t, "value": n / (ms_t * 1e-3), "unit": "updates/s",
                           "hbm_gbs": BYTES_PER_POINT_TANGENT * n / (ms_t * 1e-3) / 1e9}
         log(f"[bench] tangent: {ms_t:.3f} ms/step")
+
+    if not args.no_rk23:
+        # adaptive Bogacki-Shampine 3(2) over one load step of the same batch:
+        # the strain ramps from 0.8 eps to eps (the last step of a 5-step path)
+        eps_n = 0.8 * eps
+        a_rk = torch.empty_like(a_old)
+        steps_rk = {}
+
+        def step_rk():
+            s_, _, st, _ = api.evaluate_rk23(eps_n, eps, a_old, phase, ps.phases, h=ps.h,
+                                             sigma_out=sigma, a_out=a_rk)
+            steps_rk["last"] = st
+        tr, _, _ = time_calls(step_rk, max(3, args.steps // 4), 1, stream)
+        ms_rk = tr / max(3, args.steps // 4)
+        st = steps_rk["last"].cpu().numpy()
+        out["rk23"] = {"workload": "same 256^3 batch, strain ramp 0.8 eps -> eps over h = 0.1 s, "
+                                   "atol 1e-6, rtol 1e-3 (no tangent)",
+                       "ms_per_step": ms_rk, "value": n / (ms_rk * 1e-3), "unit": "updates/s",
+                       "accepted_steps_histogram": {int(k): int(v) for k, v in
+                                                    zip(*np.unique(st, return_counts=True))}}
+        log(f"[bench] rk23: {ms_rk:.3f} ms/step")
+        del eps_n, a_rk
 
     if args.ms_steps > 0:
         out["ms"] = ms_bench(args.ms_steps)
