@@ -260,6 +260,18 @@ def main():
                           "hbm_gbs": BYTES_PER_POINT_TANGENT * n / (ms_t * 1e-3) / 1e9}
         log(f"[bench] tangent: {ms_t:.3f} ms/step")
 
+    # the paper's conventional strategy (hand-reduced radial return, no AD)
+    # on the same batch: what the automatic evaluation costs
+    def step_cv():
+        api.evaluate_conventional(eps, a_old, phase, ps.phases, ps.h, ps.tol, ps.max_iter,
+                                  sigma_out=sigma, a_out=a_new)
+    tc, _, _ = time_calls(step_cv, max(3, args.steps // 2), 2, stream)
+    ms_cv = tc / max(3, args.steps // 2)
+    out["conventional"] = {"workload": "same 256^3 batch, radial return (scalar Newton, no AD)",
+                           "ms_per_step": ms_cv, "value": n / (ms_cv * 1e-3), "unit": "updates/s",
+                           "automatic_over_conventional_time": ms / ms_cv}
+    log(f"[bench] conventional: {ms_cv:.3f} ms/step (automatic / conventional = {ms / ms_cv:.2f})")
+
     if not args.no_rk23:
         # adaptive Bogacki-Shampine 3(2) over one load step of the same batch:
         # the strain ramps from 0.8 eps to eps (the last step of a 5-step path)

@@ -321,6 +321,24 @@ int32_t automat_server_stats(automat_server *server, automat_server_stats_t *sta
 int32_t automat_server_destroy(automat_server *server);
 
 /* ------------------------------------------------------------------------
+ * The paper's "conventional" evaluation strategy (Section "Single Implicit
+ * Euler Step" and Table "implicit_euler_timings"): the same implicit-Euler
+ * step of the same material, reduced by hand to a scalar equation for the
+ * equivalent stress (radial return), without automatic differentiation. A
+ * comparison point for automat_evaluate. The flow keeps the direction of
+ * the trial deviator and q solves
+ *   q + (3 mu + H) h eps0 ((q - sigma_y)^+ / sigma0)^n = q_tr
+ * by Newton from q_tr (monotone), stopped when a step is <= tol q.
+ * Arguments and layout as automat_evaluate_ex (no tangent, no flags);
+ * iters_out: Newton steps (0 without flow), -1 for invalid input or no
+ * convergence within max_iter. */
+int32_t automat_evaluate_conventional(int64_t n, const double *eps_new, const double *a_old,
+                                      const uint8_t *phase, const automat_params *params,
+                                      double h, double tol, int32_t max_iter, double *sigma_out,
+                                      double *a_out, int32_t *iters_out, uint64_t *nonconverged,
+                                      void *stream);
+
+/* ------------------------------------------------------------------------
  * Adaptive explicit Runge-Kutta evaluation (Section "Rosenbrock and
  * Runge-Kutta Schemes with Adaptive Step Size"; error measure on stresses as
  * in Section "Error Control"). Over one load step of length h the strain

@@ -83,6 +83,28 @@ def evaluate(eps, a_old, phase, phases, h=0.1, tol=1e-12, max_iter=50, *, tangen
     return tuple(out)
 
 
+def evaluate_conventional(eps, a_old, phase, phases, h=0.1, tol=1e-12, max_iter=50, *,
+                          a_out=None, sigma_out=None):
+    """Hand-reduced radial-return evaluation (the paper's conventional
+    strategy). Returns (sigma, a_new, iters (n,) int32, failed-point count)."""
+    eps = _field(eps, "eps", 6)
+    n, dev = eps.shape[1], eps.device
+    a_old = _field(a_old, "a_old", 6, n, dev)
+    phase = _phase_ids(phase, n, dev)
+    params = make_params(phases)
+    sigma = torch.empty_like(eps) if sigma_out is None else _field(sigma_out, "sigma_out", 6, n, dev)
+    a_new = torch.empty_like(a_old) if a_out is None else _field(a_out, "a_out", 6, n, dev)
+    iters = torch.empty(n, dtype=torch.int32, device=dev)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    with torch.cuda.device(dev):
+        rc = load().automat_evaluate_conventional(n, _ptr(eps), _ptr(a_old), _ptr(phase),
+                                                  ctypes.byref(params), float(h), float(tol),
+                                                  int(max_iter), _ptr(sigma), _ptr(a_new),
+                                                  _ptr(iters), _ptr(count), _stream(dev))
+    check("automat_evaluate_conventional", rc)
+    return sigma, a_new, iters, count
+
+
 def evaluate_rk23(eps_n, eps_new, a_old, phase, phases, h=0.1, atol=1e-6, rtol=1e-3,
                   max_steps=100000, *, a_out=None, sigma_out=None):
     """Adaptive Bogacki-Shampine 3(2) evaluation over one load step with the
