@@ -60,6 +60,8 @@ def lib():
                                            ctypes.c_int, dp, ctypes.c_double, ctypes.c_double,
                                            ctypes.c_double, ctypes.c_int, dp, dp, dp,
                                            ctypes.c_void_p, ctypes.c_void_p]
+        L.oracle_evaluate_rk12.restype = ctypes.c_int
+        L.oracle_evaluate_rk12.argtypes = L.oracle_evaluate_rk23.argtypes
         _lib = L
     return _lib
 
@@ -132,8 +134,15 @@ def backward(eps, a_old, a_new, phase, phases, h, grad_sigma=None, grad_a=None):
     return dict(grad_eps=geps, grad_a_old=gan, grad_params=gpar)
 
 
-def evaluate_rk23(eps_n, eps1, a_old, phase, phases, h=0.1, atol=1e-6, rtol=1e-3,
+def evaluate_rk12(eps_n, eps1, a_old, phase, phases, h=0.1, atol=1e-6, rtol=1e-3,
                   max_steps=100000, tangent=False):
+    """As evaluate_rk23 with the Heun-Euler 2(1) pair (the paper's ode12)."""
+    return evaluate_rk23(eps_n, eps1, a_old, phase, phases, h, atol, rtol, max_steps, tangent,
+                         _fn="oracle_evaluate_rk12")
+
+
+def evaluate_rk23(eps_n, eps1, a_old, phase, phases, h=0.1, atol=1e-6, rtol=1e-3,
+                  max_steps=100000, tangent=False, _fn="oracle_evaluate_rk23"):
     """Adaptive Bogacki-Shampine 3(2) evaluation over one load step with the
     strain moving linearly from eps_n to eps1. Returns dict(sigma, a_out,
     tangent (36, n) or None, steps (accepted, -1 on failure), rejected)."""
@@ -148,12 +157,12 @@ def evaluate_rk23(eps_n, eps1, a_old, phase, phases, h=0.1, atol=1e-6, rtol=1e-3
     tan = np.empty((36, n)) if tangent else None
     steps = np.empty(n, dtype=np.int32)
     rej = np.empty(n, dtype=np.int32)
-    rc = lib().oracle_evaluate_rk23(n, _dp(eps_n), _dp(eps1), _dp(a_old), phase.ctypes.data,
+    rc = getattr(lib(), _fn)(n, _dp(eps_n), _dp(eps1), _dp(a_old), phase.ctypes.data,
                                     par.shape[0], _dp(par), h, atol, rtol, max_steps,
                                     _dp(sigma), _dp(a_out), _dp(tan), steps.ctypes.data,
                                     rej.ctypes.data)
     if rc != 0:
-        raise ValueError("oracle_evaluate_rk23: invalid arguments")
+        raise ValueError(f"{_fn}: invalid arguments")
     return dict(sigma=sigma, a_out=a_out, tangent=tan, steps=steps, rejected=rej)
 
 

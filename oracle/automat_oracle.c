@@ -892,3 +892,154 @@ int oracle_evaluate_rk23(int64_t n, const double *eps_n, const double *eps1,
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * The lower-order pair the paper calls ode12: explicit Euler embedded in
+ * Heun's method. One step of size dt from (s, y):
+ *   k1 = f(s, y),  k2 = f(s + dt, y + dt k1),
+ *   y1 = y + dt/2 (k1 + k2)  (second order),  yh = y + dt k1  (first order).
+ * Same error measure on stresses (and tangents) and the same step size
+ * rule as above with exponent 1/2 (the lower order is 1). k1 is evaluated
+ * afresh at every step (the pair is not first-same-as-last).
+ * ------------------------------------------------------------------------ */
+static int rk12_point(const phase_t *ph, int nph, int pid, const double eps_n[6],
+                      const double eps1[6], const double an[6], double h, double atol,
+                      double rtol, int max_steps, double sigma[6], double a_out[6],
+                      double *tangent, int *rejected)
+{
+    *rejected = 0;
+    int bad = pid >= nph || !all_finite(eps_n, 6) || !all_finite(eps1, 6) || !all_finite(an, 6);
+    if (bad) {
+        for (int i = 0; i < 6; ++i) sigma[i] = a_out[i] = NAN;
+        if (tangent)
+            for (int i = 0; i < 36; ++i) tangent[i] = NAN;
+        return -1;
+    }
+    const phase_t *p = &ph[pid];
+    double C[6][6], K[6][6], de[6];
+    stiffness(p->E, p->nu, C);
+    hessian_omega_aa(p, C, K);
+    for (int i = 0; i < 6; ++i) de[i] = eps1[i] - eps_n[i];
+    const int tan = tangent != NULL;
+    double y[6], Y[36], k1[6], k2[6], yt[6], y1[6], yh[6], K1[36], K2[36], Yt[36], Y1[36];
+    double P2[6][6];
+    memcpy(y, an, sizeof y);
+    memset(Y, 0, sizeof Y);
+    double s = 0.0, dt = h, fmax_ = 5.0;
+    int accepted = 0, attempts = 0, status = 0;
+    while (s < h) {
+        if (++attempts > max_steps) {
+            status = -1;
+            break;
+        }
+        const int last = dt >= h - s;
+        if (last) dt = h - s;
+        const double th0 = s / h, th1 = last ? 1.0 : (s + dt) / h;
+        rk_rhs(p, C, eps_n, de, th0, y, k1, tan ? P2 : NULL);
+        if (tan) rk_rhs_tan(P2, C, K, th0, Y, K1);
+        for (int i = 0; i < 6; ++i) yt[i] = y[i] + dt * k1[i];
+        rk_rhs(p, C, eps_n, de, th1, yt, k2, tan ? P2 : NULL);
+        if (tan) {
+            for (int i = 0; i < 36; ++i) Yt[i] = Y[i] + dt * K1[i];
+            rk_rhs_tan(P2, C, K, th1, Yt, K2);
+        }
+        for (int i = 0; i < 6; ++i) {
+            y1[i] = y[i] + 0.5 * dt * (k1[i] + k2[i]);
+            yh[i] = y[i] + dt * k1[i];
+        }
+        double d0[6], d1[6], dh[6], z0[6], z1[6], zh[6];
+        for (int i = 0; i < 6; ++i) {
+            const double e0 = eps_n[i] + th0 * de[i], e1 = eps_n[i] + th1 * de[i];
+            d0[i] = e0 - y[i];
+            d1[i] = e1 - y1[i];
+            dh[i] = e1 - yh[i];
+        }
+        matvec(C, d0, z0);
+        matvec(C, d1, z1);
+        matvec(C, dh, zh);
+        double sum = 0.0;
+        int cnt = 6;
+        for (int i = 0; i < 6; ++i) {
+            const double r = (z1[i] - zh[i]) / rk_scale(atol, rtol, z0[i], z1[i]);
+            sum += r * r;
+        }
+        if (tan) {
+            for (int i = 0; i < 36; ++i) Y1[i] = Y[i] + 0.5 * dt * (K1[i] + K2[i]);
+            for (int j = 0; j < 6; ++j)
+                for (int i = 0; i < 6; ++i) {
+                    double t0 = th0 * C[i][j], t1 = th1 * C[i][j], tq = th1 * C[i][j];
+                    for (int q = 0; q < 6; ++q) {
+                        t0 -= C[i][q] * Y[q * 6 + j];
+                        t1 -= C[i][q] * Y1[q * 6 + j];
+                        tq -= C[i][q] * (Y[q * 6 + j] + dt * K1[q * 6 + j]);
+                    }
+                    const double r = (t1 - tq) / rk_scale(atol, rtol, t0, t1);
+                    sum += r * r;
+                }
+            cnt += 36;
+        }
+        const double err = sqrt(sum / cnt);
+        double fac = err > 0.0 ? 0.9 * pow(err, -0.5) : fmax_;
+        fac = fmin(fmax_, fmax(0.2, fac));
+        if (err <= 1.0) {
+            ++accepted;
+            s = last ? h : s + dt;
+            memcpy(y, y1, sizeof y);
+            if (tan) memcpy(Y, Y1, sizeof Y);
+            dt *= fac;
+            fmax_ = 5.0;
+        } else {
+            ++*rejected;
+            dt *= fmin(1.0, fac);
+            fmax_ = 1.0;
+        }
+    }
+    double d[6];
+    for (int i = 0; i < 6; ++i) {
+        a_out[i] = y[i];
+        d[i] = eps1[i] - y[i];
+    }
+    matvec(C, d, sigma);
+    if (tangent)
+        for (int i = 0; i < 6; ++i)
+            for (int j = 0; j < 6; ++j) {
+                double t = C[i][j];
+                for (int q = 0; q < 6; ++q) t -= C[i][q] * Y[q * 6 + j];
+                tangent[i * 6 + j] = t;
+            }
+    return status < 0 ? -1 : accepted;
+}
+
+int oracle_evaluate_rk12(int64_t n, const double *eps_n, const double *eps1,
+                         const double *a_old, const uint8_t *phase, int n_phases,
+                         const double *par, double h, double atol, double rtol, int max_steps,
+                         double *sigma, double *a_out, double *tangent, int32_t *steps,
+                         int32_t *rejected)
+{
+    phase_t ph[256];
+    if (n < 0 || !eps_n || !eps1 || !a_old || !phase || !par || !sigma || !a_out) return -1;
+    if (!(h > 0.0) || !isfinite(h) || !(atol >= 0.0) || !(rtol > 0.0) || max_steps < 1)
+        return -1;
+    if (load_all(n_phases, par, ph) != 0) return -1;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        double e0[6], e1[6], an[6], s[6], ao[6], t[36];
+        for (int c = 0; c < 6; ++c) {
+            e0[c] = eps_n[c * n + i];
+            e1[c] = eps1[c * n + i];
+            an[c] = a_old[c * n + i];
+        }
+        int rej = 0;
+        int st = rk12_point(ph, n_phases, phase[i], e0, e1, an, h, atol, rtol, max_steps, s, ao,
+                            tangent ? t : NULL, &rej);
+        for (int c = 0; c < 6; ++c) {
+            sigma[c * n + i] = s[c];
+            a_out[c * n + i] = ao[c];
+        }
+        if (tangent)
+            for (int c = 0; c < 36; ++c) tangent[c * n + i] = t[c];
+        if (steps) steps[i] = st;
+        if (rejected) rejected[i] = rej;
+    }
+    return 0;
+}
