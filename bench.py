@@ -155,7 +155,7 @@ def main():
                     help="host processes generating the requests' microstructures")
     ap.add_argument("--ms-steps", type=int, default=20,
                     help="load steps of the 128^3 Moulinec-Suquet run (0 skips it)")
-    ap.add_argument("--no-rk23", action="store_true", help="skip the adaptive ode23 leg")
+    ap.add_argument("--no-rk23", action="store_true", help="skip the adaptive ode23 and ode12 legs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (known traffic: 1 GiB read, "
                          "1 GiB written) so profiler byte counters can be scaled")
@@ -273,25 +273,27 @@ def main():
     log(f"[bench] conventional: {ms_cv:.3f} ms/step (automatic / conventional = {ms / ms_cv:.2f})")
 
     if not args.no_rk23:
-        # adaptive Bogacki-Shampine 3(2) over one load step of the same batch:
+        # adaptive explicit Runge-Kutta over one load step of the same batch:
         # the strain ramps from 0.8 eps to eps (the last step of a 5-step path)
         eps_n = 0.8 * eps
         a_rk = torch.empty_like(a_old)
-        steps_rk = {}
+        for pair, fn in (("rk23", api.evaluate_rk23), ("rk12", api.evaluate_rk12)):
+            steps_rk = {}
 
-        def step_rk():
-            s_, _, st, _ = api.evaluate_rk23(eps_n, eps, a_old, phase, ps.phases, h=ps.h,
-                                             sigma_out=sigma, a_out=a_rk)
-            steps_rk["last"] = st
-        tr, _, _ = time_calls(step_rk, max(3, args.steps // 4), 1, stream)
-        ms_rk = tr / max(3, args.steps // 4)
-        st = steps_rk["last"].cpu().numpy()
-        out["rk23"] = {"workload": "same 256^3 batch, strain ramp 0.8 eps -> eps over h = 0.1 s, "
-                                   "atol 1e-6, rtol 1e-3 (no tangent)",
-                       "ms_per_step": ms_rk, "value": n / (ms_rk * 1e-3), "unit": "updates/s",
-                       "accepted_steps_histogram": {int(k): int(v) for k, v in
-                                                    zip(*np.unique(st, return_counts=True))}}
-        log(f"[bench] rk23: {ms_rk:.3f} ms/step")
+            def step_rk():
+                s_, _, st, _ = fn(eps_n, eps, a_old, phase, ps.phases, h=ps.h,
+                                  sigma_out=sigma, a_out=a_rk)
+                steps_rk["last"] = st
+            tr, _, _ = time_calls(step_rk, max(3, args.steps // 4), 1, stream)
+            ms_rk = tr / max(3, args.steps // 4)
+            st = steps_rk["last"].cpu().numpy()
+            name = "Bogacki-Shampine 3(2)" if pair == "rk23" else "Heun-Euler 2(1)"
+            out[pair] = {"workload": f"same 256^3 batch, {name}, strain ramp 0.8 eps -> eps over "
+                                     "h = 0.1 s, atol 1e-6, rtol 1e-3 (no tangent)",
+                         "ms_per_step": ms_rk, "value": n / (ms_rk * 1e-3), "unit": "updates/s",
+                         "accepted_steps_histogram": {int(k): int(v) for k, v in
+                                                      zip(*np.unique(st, return_counts=True))}}
+            log(f"[bench] {pair}: {ms_rk:.3f} ms/step")
         del eps_n, a_rk
 
     if args.ms_steps > 0:

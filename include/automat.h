@@ -366,6 +366,18 @@ int32_t automat_evaluate_rk23(int64_t n, const double *eps_n, const double *eps_
                               int32_t max_steps, double *sigma_out, double *a_out,
                               int32_t *steps_out, uint64_t *nonconverged, void *stream);
 
+/* The lower-order embedded pair of the same section (the paper's ode12):
+ * explicit Euler inside Heun's method, k1 = f(t, a), k2 = f(t + dt, a + dt k1),
+ * a_{2nd} = a + dt/2 (k1 + k2), a_{1st} = a + dt k1; error measure, step
+ * acceptance, first try and growth limits as automat_evaluate_rk23 with the
+ * step factor 0.9 err^(-1/2). Arguments, layout, ownership and errors as
+ * automat_evaluate_rk23. */
+int32_t automat_evaluate_rk12(int64_t n, const double *eps_n, const double *eps_new,
+                              const double *a_old, const uint8_t *phase,
+                              const automat_params *params, double h, double atol, double rtol,
+                              int32_t max_steps, double *sigma_out, double *a_out,
+                              int32_t *steps_out, uint64_t *nonconverged, void *stream);
+
 /* Human-readable text of a return code. */
 const char *automat_strerror(int32_t code);
 

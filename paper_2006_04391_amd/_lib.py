@@ -95,6 +95,8 @@ SIGNATURES = {
     "automat_server_destroy": (_i32, [_vp]),
     "automat_evaluate_rk23": (_i32, [_i64, _vp, _vp, _vp, _vp, _vp, _dbl, _dbl, _dbl, _i32, _vp,
                                       _vp, _vp, _vp, _vp]),
+    "automat_evaluate_rk12": (_i32, [_i64, _vp, _vp, _vp, _vp, _vp, _dbl, _dbl, _dbl, _i32, _vp,
+                                      _vp, _vp, _vp, _vp]),
     "automat_evaluate_conventional": (_i32, [_i64, _vp, _vp, _vp, _vp, _dbl, _dbl, _i32, _vp, _vp,
                                               _vp, _vp, _vp]),
     "automat_strerror": (ctypes.c_char_p, [_i32]),

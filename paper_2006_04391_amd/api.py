@@ -106,7 +106,7 @@ def evaluate_conventional(eps, a_old, phase, phases, h=0.1, tol=1e-12, max_iter=
 
 
 def evaluate_rk23(eps_n, eps_new, a_old, phase, phases, h=0.1, atol=1e-6, rtol=1e-3,
-                  max_steps=100000, *, a_out=None, sigma_out=None):
+                  max_steps=100000, *, a_out=None, sigma_out=None, _entry="automat_evaluate_rk23"):
     """Adaptive Bogacki-Shampine 3(2) evaluation over one load step with the
     strain moving linearly from eps_n to eps_new. Returns (sigma, a_new,
     steps (n,) int32, failed-point count)."""
@@ -121,12 +121,19 @@ def evaluate_rk23(eps_n, eps_new, a_old, phase, phases, h=0.1, atol=1e-6, rtol=1
     steps = torch.empty(n, dtype=torch.int32, device=dev)
     count = torch.zeros(1, dtype=torch.int64, device=dev)
     with torch.cuda.device(dev):
-        rc = load().automat_evaluate_rk23(n, _ptr(eps_n), _ptr(eps_new), _ptr(a_old), _ptr(phase),
-                                          ctypes.byref(params), float(h), float(atol), float(rtol),
-                                          int(max_steps), _ptr(sigma), _ptr(a_new), _ptr(steps),
-                                          _ptr(count), _stream(dev))
-    check("automat_evaluate_rk23", rc)
+        rc = getattr(load(), _entry)(n, _ptr(eps_n), _ptr(eps_new), _ptr(a_old), _ptr(phase),
+                                     ctypes.byref(params), float(h), float(atol), float(rtol),
+                                     int(max_steps), _ptr(sigma), _ptr(a_new), _ptr(steps),
+                                     _ptr(count), _stream(dev))
+    check(_entry, rc)
     return sigma, a_new, steps, count
+
+
+def evaluate_rk12(eps_n, eps_new, a_old, phase, phases, h=0.1, atol=1e-6, rtol=1e-3,
+                  max_steps=100000, *, a_out=None, sigma_out=None):
+    """As evaluate_rk23 with the Heun-Euler 2(1) pair (ode12)."""
+    return evaluate_rk23(eps_n, eps_new, a_old, phase, phases, h, atol, rtol, max_steps,
+                         a_out=a_out, sigma_out=sigma_out, _entry="automat_evaluate_rk12")
 
 
 def evaluate_backward(eps, a_old, a_new, phase, phases, h, grad_sigma=None, grad_a=None, *,

@@ -17,6 +17,11 @@
 // err = rms_i (z1_i - zh_i) / (atol + rtol max(|z0_i|, |z1_i|)); accept if
 // err <= 1; dt *= min(fmax, max(1/5, 0.9 err^(-1/3))) with fmax = 5, or 1
 // after a rejection; the first try is the whole load step.
+//
+// The same kernel also runs the lower-order pair of the same section, ode12:
+// explicit Euler embedded in Heun's method, k1 = f(s, y) (recomputed every
+// step), k2 = f(s + dt, y + dt k1), y1 = y + dt/2 (k1 + k2), yh = y + dt k1,
+// with the step factor 0.9 err^(-1/2).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -66,7 +71,8 @@ __device__ __forceinline__ void rk_stress(const Model::Phase &p, const double *e
     Model::stress(p, e, a, z);
 }
 
-__global__ __launch_bounds__(kBlock) void rk23_kernel(const Rk23Args args) {
+template <bool BS23>
+__global__ __launch_bounds__(kBlock) void rk_kernel(const Rk23Args args) {
     __shared__ Model::Phase tab[AUTOMAT_MAX_PHASES];
     for (int k = threadIdx.x; k < args.n_phases; k += blockDim.x) {
         Model::Phase q = args.phases[k];
@@ -97,7 +103,7 @@ __global__ __launch_bounds__(kBlock) void rk23_kernel(const Rk23Args args) {
         int status = valid ? 1 : -1;  // elastic points: one (trivial) step
         double k1[6], z0[6];
         if (flow) {
-            rk_rhs(p, e0, de, 0.0, y, k1);
+            if (BS23) rk_rhs(p, e0, de, 0.0, y, k1);
             rk_stress(p, e0, de, 0.0, y, z0);
         }
         double s = 0.0, dt = h, fmx = 5.0;
@@ -113,23 +119,34 @@ __global__ __launch_bounds__(kBlock) void rk23_kernel(const Rk23Args args) {
             }
             const bool last = dt >= h - s;
             if (last) dt = h - s;
-            const double th2 = (s + 0.5 * dt) / h, th3 = (s + 0.75 * dt) / h;
             const double th4 = last ? 1.0 : (s + dt) / h;
-            double yt[6], k2[6], k3[6], k4[6], y1[6], yh[6];
+            double y1[6], yh[6], k4[6];
+            if constexpr (BS23) {
+                const double th2 = (s + 0.5 * dt) / h, th3 = (s + 0.75 * dt) / h;
+                double yt[6], k2[6], k3[6];
 #pragma unroll
-            for (int c = 0; c < 6; ++c) yt[c] = y[c] + 0.5 * dt * k1[c];
-            rk_rhs(p, e0, de, th2, yt, k2);
+                for (int c = 0; c < 6; ++c) yt[c] = y[c] + 0.5 * dt * k1[c];
+                rk_rhs(p, e0, de, th2, yt, k2);
 #pragma unroll
-            for (int c = 0; c < 6; ++c) yt[c] = y[c] + 0.75 * dt * k2[c];
-            rk_rhs(p, e0, de, th3, yt, k3);
+                for (int c = 0; c < 6; ++c) yt[c] = y[c] + 0.75 * dt * k2[c];
+                rk_rhs(p, e0, de, th3, yt, k3);
 #pragma unroll
-            for (int c = 0; c < 6; ++c)
-                y1[c] = y[c] + dt * (2.0 / 9.0 * k1[c] + 1.0 / 3.0 * k2[c] + 4.0 / 9.0 * k3[c]);
-            rk_rhs(p, e0, de, th4, y1, k4);
+                for (int c = 0; c < 6; ++c)
+                    y1[c] = y[c] + dt * (2.0 / 9.0 * k1[c] + 1.0 / 3.0 * k2[c] + 4.0 / 9.0 * k3[c]);
+                rk_rhs(p, e0, de, th4, y1, k4);
 #pragma unroll
-            for (int c = 0; c < 6; ++c)
-                yh[c] = y[c] + dt * (7.0 / 24.0 * k1[c] + 0.25 * k2[c] + 1.0 / 3.0 * k3[c] +
-                                     0.125 * k4[c]);
+                for (int c = 0; c < 6; ++c)
+                    yh[c] = y[c] + dt * (7.0 / 24.0 * k1[c] + 0.25 * k2[c] + 1.0 / 3.0 * k3[c] +
+                                         0.125 * k4[c]);
+            } else {
+                double k2[6];
+                rk_rhs(p, e0, de, s / h, y, k1);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) yh[c] = y[c] + dt * k1[c];
+                rk_rhs(p, e0, de, th4, yh, k2);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) y1[c] = y[c] + 0.5 * dt * (k1[c] + k2[c]);
+            }
             double z1[6], zh[6];
             rk_stress(p, e0, de, th4, y1, z1);
             rk_stress(p, e0, de, th4, yh, zh);
@@ -140,7 +157,9 @@ __global__ __launch_bounds__(kBlock) void rk23_kernel(const Rk23Args args) {
                 sum += r * r;
             }
             const double err = sqrt(sum / 6.0);
-            double fac = err > 0.0 ? 0.9 * fm::exp(-fm::log(err) * (1.0 / 3.0)) : fmx;
+            double fac = fmx;
+            if (err > 0.0)
+                fac = BS23 ? 0.9 * fm::exp(-fm::log(err) * (1.0 / 3.0)) : 0.9 / sqrt(err);
             fac = fmin(fmx, fmax(0.2, fac));
             if (err <= 1.0) {
                 ++accepted;
@@ -148,7 +167,7 @@ __global__ __launch_bounds__(kBlock) void rk23_kernel(const Rk23Args args) {
 #pragma unroll
                 for (int c = 0; c < 6; ++c) {
                     y[c] = y1[c];
-                    k1[c] = k4[c];
+                    if (BS23) k1[c] = k4[c];  // first same as last
                     z0[c] = z1[c];
                 }
                 dt *= fac;
@@ -187,12 +206,10 @@ __global__ __launch_bounds__(kBlock) void rk23_kernel(const Rk23Args args) {
 
 using namespace automat;
 
-extern "C" int32_t automat_evaluate_rk23(int64_t n, const double *eps_n, const double *eps_new,
-                                         const double *a_old, const uint8_t *phase,
-                                         const automat_params *params, double h, double atol,
-                                         double rtol, int32_t max_steps, double *sigma_out,
-                                         double *a_out, int32_t *steps_out,
-                                         uint64_t *nonconverged, void *stream) {
+static int32_t launch_rk(bool bs23, int64_t n, const double *eps_n, const double *eps_new,
+                         const double *a_old, const uint8_t *phase, const automat_params *params,
+                         double h, double atol, double rtol, int32_t max_steps, double *sigma_out,
+                         double *a_out, int32_t *steps_out, uint64_t *nonconverged, void *stream) {
     if (n < 0) return AUTOMAT_EINVAL;
     if (!std::isfinite(h) || !(h > 0.0) || !std::isfinite(atol) || !(atol >= 0.0) ||
         !std::isfinite(rtol) || !(rtol > 0.0) || max_steps < 1)
@@ -223,8 +240,31 @@ extern "C" int32_t automat_evaluate_rk23(int64_t n, const double *eps_n, const d
     const int64_t tiles = (n + kBlock - 1) / kBlock;
     const int64_t cap = (int64_t)cus * 4;
     const int grid = (int)(tiles < cap ? tiles : cap);
-    hipLaunchKernelGGL(rk23_kernel, dim3(grid), dim3(kBlock), 0,
-                       reinterpret_cast<hipStream_t>(stream), args);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (bs23)
+        hipLaunchKernelGGL(rk_kernel<true>, dim3(grid), dim3(kBlock), 0, st, args);
+    else
+        hipLaunchKernelGGL(rk_kernel<false>, dim3(grid), dim3(kBlock), 0, st, args);
     if (hipGetLastError() != hipSuccess) return AUTOMAT_EHIP;
     return AUTOMAT_OK;
+}
+
+extern "C" int32_t automat_evaluate_rk23(int64_t n, const double *eps_n, const double *eps_new,
+                                         const double *a_old, const uint8_t *phase,
+                                         const automat_params *params, double h, double atol,
+                                         double rtol, int32_t max_steps, double *sigma_out,
+                                         double *a_out, int32_t *steps_out,
+                                         uint64_t *nonconverged, void *stream) {
+    return launch_rk(true, n, eps_n, eps_new, a_old, phase, params, h, atol, rtol, max_steps,
+                     sigma_out, a_out, steps_out, nonconverged, stream);
+}
+
+extern "C" int32_t automat_evaluate_rk12(int64_t n, const double *eps_n, const double *eps_new,
+                                         const double *a_old, const uint8_t *phase,
+                                         const automat_params *params, double h, double atol,
+                                         double rtol, int32_t max_steps, double *sigma_out,
+                                         double *a_out, int32_t *steps_out,
+                                         uint64_t *nonconverged, void *stream) {
+    return launch_rk(false, n, eps_n, eps_new, a_old, phase, params, h, atol, rtol, max_steps,
+                     sigma_out, a_out, steps_out, nonconverged, stream);
 }

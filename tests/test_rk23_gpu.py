@@ -1,6 +1,6 @@
-"""Adaptive Bogacki-Shampine 3(2) evaluation on the GPU vs the oracle, point
-by point on the same seeded inputs (same accepted steps, results within the
-parity bar)."""
+"""Adaptive explicit Runge-Kutta evaluation on the GPU (Bogacki-Shampine 3(2)
+and Heun-Euler 2(1)) vs the oracle, point by point on the same seeded inputs
+(same accepted steps, results within the parity bar)."""
 import numpy as np
 import pytest
 
@@ -12,12 +12,15 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-def _run(e0, ps, h, **kw):
+PAIRS = ["rk23", "rk12"]
+
+
+def _run(e0, ps, h, pair="rk23", **kw):
     from paper_2006_04391_amd import api
-    sig, a, steps, cnt = api.evaluate_rk23(T(e0), T(ps.eps), T(ps.a_old), T(ps.phase), ps.phases,
-                                           h=h, **kw)
+    fn = getattr(api, "evaluate_" + pair)
+    sig, a, steps, cnt = fn(T(e0), T(ps.eps), T(ps.a_old), T(ps.phase), ps.phases, h=h, **kw)
     torch.cuda.synchronize()
-    ref = oracle.evaluate_rk23(e0, ps.eps, ps.a_old, ps.phase, ps.phases, h=h, **kw)
+    ref = getattr(oracle, "evaluate_" + pair)(e0, ps.eps, ps.a_old, ps.phase, ps.phases, h=h, **kw)
     return dict(sigma=N(sig), a_out=N(a), steps=N(steps), count=int(cnt.item())), ref
 
 
@@ -29,44 +32,49 @@ def _check(g, ref):
     assert g["count"] == int((ref["steps"] < 0).sum())
 
 
+@pytest.mark.parametrize("pair", PAIRS)
 @pytest.mark.parametrize("preset,n,seed", [("config", 4133, 1), ("paper", 1031, 2)])
-def test_ramp_parity(preset, n, seed):
+def test_ramp_parity(preset, n, seed, pair):
     phases = inputs.config_phases() if preset == "config" else inputs.paper_phases()
     # loads that make the matrix flow enough for several steps
     e11, h = (2e-2, 10.0) if preset == "config" else (4e-3, 1.0)
     ps = inputs.points_random(n, seed=seed, phases=phases, e11=e11, std=3e-4, a_std=1e-4)
     e0 = 0.5 * ps.eps + 1e-4 * np.random.default_rng(seed).normal(size=ps.eps.shape)
-    g, ref = _run(e0, ps, h=h)
+    g, ref = _run(e0, ps, h=h, pair=pair)
     assert ref["steps"].max() > 1
     _check(g, ref)
 
 
-def test_tight_tolerances_many_steps():
+@pytest.mark.parametrize("pair,rtol", [("rk23", 1e-9), ("rk12", 1e-6)])
+def test_tight_tolerances_many_steps(pair, rtol):
     ps = inputs.points_random(700, seed=5, phases=inputs.paper_phases(), e11=6e-3, std=5e-4)
     e0 = np.zeros_like(ps.eps)
-    g, ref = _run(e0, ps, h=1.0, atol=1e-12, rtol=1e-9)
+    g, ref = _run(e0, ps, h=1.0, pair=pair, atol=1e-3 * rtol, rtol=rtol)
     assert ref["steps"].max() > 20
     _check(g, ref)
 
 
-def test_invalid_points_and_step_limit():
+@pytest.mark.parametrize("pair", PAIRS)
+def test_invalid_points_and_step_limit(pair):
     ps = inputs.points_random(300, seed=6, phases=inputs.paper_phases(), e11=6e-3, std=5e-4)
     ps.eps[0, 7] = np.inf
     ps.phase[11] = 9
     e0 = np.zeros_like(ps.eps)
-    g, ref = _run(e0, ps, h=1.0, max_steps=3)
+    g, ref = _run(e0, ps, h=1.0, pair=pair, max_steps=3)
     assert (ref["steps"] < 0).sum() > 2 and g["steps"][7] == -1 and g["steps"][11] == -1
     _check(g, ref)
 
 
-def test_empty_and_invalid_arguments():
+@pytest.mark.parametrize("pair", PAIRS)
+def test_empty_and_invalid_arguments(pair):
     from paper_2006_04391_amd import api, _lib
+    fn = getattr(api, "evaluate_" + pair)
     ps = inputs.points_random(10, seed=7, phases=inputs.config_phases())
     z = T(np.zeros_like(ps.eps))
     with pytest.raises(_lib.AutomatError):
-        api.evaluate_rk23(z, T(ps.eps), T(ps.a_old), T(ps.phase), ps.phases, h=0.0)
+        fn(z, T(ps.eps), T(ps.a_old), T(ps.phase), ps.phases, h=0.0)
     with pytest.raises(_lib.AutomatError):
-        api.evaluate_rk23(z, T(ps.eps), T(ps.a_old), T(ps.phase), ps.phases, rtol=0.0)
+        fn(z, T(ps.eps), T(ps.a_old), T(ps.phase), ps.phases, rtol=0.0)
     e = torch.empty((6, 0), dtype=torch.float64, device="cuda")
-    out = api.evaluate_rk23(e, e, e, torch.empty(0, dtype=torch.uint8, device="cuda"), ps.phases)
+    out = fn(e, e, e, torch.empty(0, dtype=torch.uint8, device="cuda"), ps.phases)
     assert out[0].shape == (6, 0)
