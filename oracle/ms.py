@@ -14,6 +14,25 @@ iteration):
 and, once converged (or after a fixed number of iterations), one more
 material sweep at the final strain that commits a_{n+1}. Fields are (6, n)
 with n = nz * ny * nx, x fastest.
+
+Driver extensions (the paper's Section "Example": the uniaxial
+tension-compression test under mixed boundary conditions, and the reference
+stiffness that is either fixed from the elastic stiffness or adjusted to the
+tangent stiffness at the start of every load step):
+
+* mixed boundary conditions: components in the stress-controlled set S take
+  the macroscopic stress S_bar, the others the macroscopic strain E_bar.
+  The zero frequency of every update is the macroscopic strain E that makes
+  the reference medium's average stress meet the targets,
+  mean(tau) + C0 E = S_bar on S, E = E_bar elsewhere (a linear solve);
+  at the fixed point mean(sigma) = mean(tau) + C0 mean(eps) = S_bar on S.
+  The load step's initial guess shifts the previous field by dE with
+  dE = E_bar - E_prev off S and C0[S,S] dE_S = -C0[S,F] dE_F;
+* reference update: after that shift, a material sweep with tangent gives the
+  isotropic part of every local tangent (projection onto the isotropic
+  fourth-order tensors, written on the full tensor), and C0 takes the means
+  of the smallest and largest of those Lame constants, the rule the fixed
+  reference applies to the elastic constants.
 """
 from __future__ import annotations
 
@@ -65,45 +84,109 @@ def _gamma_unit(T, q, lam0, mu0):
 
 def gamma_apply(tau_hat, shape, lam0, mu0):
     """-Gamma0 : tau^ on the half spectrum (the zero frequency is set by the
-    caller). A component k = N_d/2 of an even dimension stands for both
-    +N_d/2 and -N_d/2; the operator is averaged over those sign choices,
-    which keeps the spectrum Hermitian (and equals the continuous operator
-    on the pure Nyquist axes, the operator being even in xi)."""
+    caller). Where a component sits at the Nyquist index N_d/2 of an even
+    dimension and another component is non-zero, +N_d/2 and -N_d/2 are one
+    index but give different directions q; there the operator is the
+    reference compliance C0^-1 (so the converged stress has no content at
+    those frequencies and the fixed point does not depend on C0). Elsewhere,
+    pure Nyquist axes included (the operator is even in q), it is the
+    continuous operator."""
     F, nyq = _freqs(shape)
     T = np.empty((3, 3) + tau_hat.shape[1:], dtype=complex)
     for c, (i, j) in enumerate(VOIGT_PAIRS):
         T[i, j] = tau_hat[c]
         T[j, i] = tau_hat[c]
-    out = np.zeros_like(tau_hat)
-    count = np.zeros(tau_hat.shape[1:])
-    for sx in (1.0, -1.0):
-        for sy in (1.0, -1.0):
-            for sz in (1.0, -1.0):
-                sgn = np.array([sx, sy, sz])
-                # a sign flip applies only where that component is at Nyquist
-                use = np.ones(tau_hat.shape[1:], dtype=bool)
-                for d in range(3):
-                    if sgn[d] < 0:
-                        use &= nyq[d]
-                q = F * np.where(nyq, sgn[:, None, None, None], 1.0)
-                norm = np.sqrt((q ** 2).sum(axis=0))
-                norm[norm == 0] = 1.0
-                g = _gamma_unit(T, q / norm, lam0, mu0)
-                out += np.where(use, g, 0.0)
-                count += use
-    return out / count
+    norm = np.sqrt((F ** 2).sum(axis=0))
+    norm[norm == 0] = 1.0
+    out = _gamma_unit(T, F / norm, lam0, mu0)
+    ambiguous = nyq.any(axis=0) & ((F != 0).sum(axis=0) >= 2)
+    S0 = np.linalg.inv(voigt_stiffness(lam0, mu0))
+    comp = -np.einsum("cd,d...->c...", S0, tau_hat)
+    return np.where(ambiguous[None], comp, out)
+
+
+def voigt_stiffness(lam, mu):
+    """Isotropic stiffness in engineering Voigt form (stress = C @ strain)."""
+    C = np.zeros((6, 6))
+    C[:3, :3] = lam
+    C[[0, 1, 2], [0, 1, 2]] += 2.0 * mu
+    C[[3, 4, 5], [3, 4, 5]] = mu
+    return C
+
+
+def full_tensor(tan):
+    """(36, n) row-major engineering-Voigt stiffnesses -> (3, 3, 3, 3, n)
+    tensors with sigma_ij = C_ijkl eps_kl (a shear column of the Voigt form
+    acts on the engineering strain 2 eps_kl, shared by kl and lk, so every
+    tensor entry equals its Voigt entry)."""
+    V = np.asarray(tan).reshape(6, 6, -1)
+    idx = {}
+    for c, (i, j) in enumerate(VOIGT_PAIRS):
+        idx[(i, j)] = idx[(j, i)] = c
+    T = np.empty((3, 3, 3, 3, V.shape[2]))
+    for i in range(3):
+        for j in range(3):
+            for k in range(3):
+                for l in range(3):
+                    T[i, j, k, l] = V[idx[(i, j)], idx[(k, l)]]
+    return T
+
+
+def isotropic_part(tan):
+    """Lame constants (lam, mu) of the isotropic part of each stiffness:
+    C_iso = 3K P1 + 2mu P2 with the projectors P1 = I x I / 3 and
+    P2 = I_sym - P1, K = (I : C : I) / 9, 2mu = (P2 :: C) / 5."""
+    T = full_tensor(tan)
+    c_iijj = np.einsum("iijj...->...", T)
+    c_ijij = np.einsum("ijij...->...", T)
+    K = c_iijj / 9.0
+    mu = (c_ijij - c_iijj / 3.0) / 10.0
+    return K - 2.0 * mu / 3.0, mu
+
+
+def reference_from_tangent(tan):
+    lam, mu = isotropic_part(tan)
+    return 0.5 * (np.nanmin(lam) + np.nanmax(lam)), 0.5 * (np.nanmin(mu) + np.nanmax(mu))
+
+
+def _macro_strain(tau_mean, E_bar, S_bar, smask, lam0, mu0):
+    """E with E = E_bar off the stress-controlled set S and
+    (tau_mean + C0 E)_S = S_bar_S."""
+    E = np.array(E_bar, dtype=np.float64)
+    S = np.array([bool(smask >> c & 1) for c in range(6)])
+    if S.any():
+        C0 = voigt_stiffness(lam0, mu0)
+        F = ~S
+        rhs = np.asarray(S_bar, dtype=np.float64)[S] - tau_mean[S] - C0[np.ix_(S, F)] @ E[F]
+        E[S] = np.linalg.solve(C0[np.ix_(S, S)], rhs)
+    return E
 
 
 def ms_step(eps, a, phase, phases, shape, E, E_prev, h, lam0=None, mu0=None, tol=1e-6,
-            max_iter=1000, fixed_iter=False, newton_tol=1e-12, newton_max_iter=50):
-    """One load step. Returns dict(eps, a, sigma, sigma_mean, iters, residual)."""
+            max_iter=1000, fixed_iter=False, newton_tol=1e-12, newton_max_iter=50,
+            stress_mask=0, S_macro=None, ref_update=False):
+    """One load step. E is the macroscopic strain (its stress-controlled
+    components are ignored), E_prev the macroscopic strain the previous step
+    reached. Returns dict(eps, a, sigma, sigma_mean, E (reached), iters,
+    residual, lam0, mu0 (the reference used))."""
     if lam0 is None or mu0 is None:
         lam0, mu0 = reference_medium(phases)
     nz, ny, nx = shape
     n = nx * ny * nz
     E = np.asarray(E, dtype=np.float64)
-    eps = np.array(eps, dtype=np.float64) + (E - np.asarray(E_prev, dtype=np.float64))[:, None]
-    En = max(np.sqrt(tensor_sq(E)), 1e-300)
+    E_prev = np.asarray(E_prev, dtype=np.float64)
+    S_bar = np.zeros(6) if S_macro is None else np.asarray(S_macro, dtype=np.float64)
+    S = np.array([bool(stress_mask >> c & 1) for c in range(6)])
+    dE = E - E_prev
+    if S.any():
+        C0 = voigt_stiffness(lam0, mu0)
+        dE[S] = np.linalg.solve(C0[np.ix_(S, S)], -C0[np.ix_(S, ~S)] @ dE[~S])
+    eps = np.array(eps, dtype=np.float64) + dE[:, None]
+    Ecur = E_prev + dE
+    if ref_update:
+        rt = evaluate(eps, a, phase, phases, h=h, tol=newton_tol, max_iter=newton_max_iter,
+                      tangent=True)
+        lam0, mu0 = reference_from_tangent(rt["tangent"])
     err = 0.0
     it = 0
     for it in range(1, max_iter + 1):
@@ -114,12 +197,14 @@ def ms_step(eps, a, phase, phases, shape, E, E_prev, h, lam0=None, mu0=None, tol
         tau[3:] -= mu0 * eps[3:]
         th = scipy.fft.rfftn(tau.reshape(6, nz, ny, nx), axes=(1, 2, 3))
         eh = gamma_apply(th, shape, lam0, mu0)
-        eh[:, 0, 0, 0] = E * n
+        Ecur = _macro_strain(th[:, 0, 0, 0].real / n, E, S_bar, stress_mask, lam0, mu0)
+        eh[:, 0, 0, 0] = Ecur * n
         new = scipy.fft.irfftn(eh, s=(nz, ny, nx), axes=(1, 2, 3)).reshape(6, n)
+        En = max(np.sqrt(tensor_sq(Ecur)), 1e-300)
         err = np.sqrt(np.mean(tensor_sq(new - eps))) / En
         eps = new
         if not fixed_iter and err <= tol:
             break
     r = evaluate(eps, a, phase, phases, h=h, tol=newton_tol, max_iter=newton_max_iter)
     return dict(eps=eps, a=r["a_out"], sigma=r["sigma"], sigma_mean=r["sigma"].mean(axis=1),
-                iters=it, residual=err)
+                E=Ecur, iters=it, residual=err, lam0=lam0, mu0=mu0)

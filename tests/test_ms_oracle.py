@@ -130,8 +130,9 @@ def test_viscoplastic_step_commits_state_and_relaxes():
 
 
 def _gamma_full(tau_full, shape, lam0, mu0):
-    """The averaged operator on the full (signed) frequency grid, for every
-    frequency: components at +-N/2 are averaged over both signs."""
+    """The operator on the full (signed) frequency grid: the reference
+    compliance where a Nyquist component meets another non-zero component,
+    the continuous operator at the signed frequency elsewhere."""
     nz, ny, nx = shape
     F = np.stack(np.broadcast_arrays(np.fft.fftfreq(nx)[None, None, :],
                                      np.fft.fftfreq(ny)[None, :, None],
@@ -141,20 +142,19 @@ def _gamma_full(tau_full, shape, lam0, mu0):
     for c, (i, j) in enumerate(oms.VOIGT_PAIRS):
         T[i, j] = tau_full[c]
         T[j, i] = tau_full[c]
-    acc = np.zeros_like(tau_full)
-    cnt = np.zeros(tau_full.shape[1:])
-    for signs in np.ndindex(2, 2, 2):
-        sgn = np.array([1.0 - 2 * s_ for s_ in signs])
-        use = np.ones(tau_full.shape[1:], dtype=bool)
-        for d in range(3):
-            if sgn[d] < 0:
-                use &= nyq[d]
-        q = np.where(nyq, np.abs(F) * sgn[:, None, None, None], F)
-        nrm = np.sqrt((q ** 2).sum(axis=0))
-        nrm[nrm == 0] = 1.0
-        acc += np.where(use, oms._gamma_unit(T, q / nrm, lam0, mu0), 0.0)
-        cnt += use
-    return acc / cnt
+    nrm = np.sqrt((F ** 2).sum(axis=0))
+    nrm[nrm == 0] = 1.0
+    cont = oms._gamma_unit(T, F / nrm, lam0, mu0)
+    amb = nyq.any(axis=0) & ((F != 0).sum(axis=0) >= 2)
+    comp = np.empty_like(tau_full)
+    for idx in np.ndindex(*tau_full.shape[1:]):
+        if amb[idx]:
+            t = tau_full[(slice(None),) + idx]
+            st = T[(slice(None), slice(None)) + idx]
+            # isotropic compliance in tensor form: e = (s - lam0/(3 lam0 + 2 mu0) tr(s) I) / (2 mu0)
+            e = (st - lam0 / (3 * lam0 + 2 * mu0) * np.trace(st) * np.eye(3)) / (2 * mu0)
+            comp[(slice(None),) + idx] = -_voigt_from_sym(e)
+    return np.where(amb[None], comp, cont)
 
 
 @pytest.mark.parametrize("shape", [(6, 8, 10), (5, 7, 9), (4, 6, 6)])
@@ -173,6 +173,27 @@ def test_green_operator_keeps_fields_real(shape):
     e_full = np.fft.ifftn(full, axes=(1, 2, 3))
     assert np.abs(e_full.imag).max() <= 1e-12 * np.abs(e_full.real).max()
     np.testing.assert_allclose(e_half, e_full.real, rtol=0, atol=1e-12 * np.abs(e_half).max())
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 8), (6, 7, 8)])
+def test_fixed_point_does_not_depend_on_the_reference(shape):
+    """Two reference media (both stiff enough for convergence) give the same
+    converged fields on a heterogeneous cell with even dimensions."""
+    nz, ny, nx = shape
+    n = nx * ny * nz
+    phase = (np.random.default_rng(2).random(n) < 0.3).astype(np.uint8)
+    ph = [ELASTIC(2500.0, 0.35), ELASTIC(72000.0, 0.22)]
+    z = np.zeros((6, n))
+    E = np.array([1e-3, -2e-4, 3e-4, 5e-4, 0, -4e-4])
+    lam0, mu0 = oms.reference_medium(ph)
+    r1 = oms.ms_step(z, z, phase, ph, shape, E, np.zeros(6), 0.1, lam0=lam0, mu0=mu0, tol=1e-14,
+                     max_iter=3000)
+    r2 = oms.ms_step(z, z, phase, ph, shape, E, np.zeros(6), 0.1, lam0=1.7 * lam0,
+                     mu0=1.4 * mu0, tol=1e-14, max_iter=3000)
+    assert r1["residual"] <= 1e-14 and r2["residual"] <= 1e-14
+    scale = np.abs(r1["sigma"]).max()
+    assert np.abs(r1["sigma"] - r2["sigma"]).max() <= 1e-10 * scale
+    assert np.abs(r1["eps"] - r2["eps"]).max() <= 1e-10 * np.abs(r1["eps"]).max()
 
 
 def test_central_differences_of_the_scheme_give_the_laminate_stiffness():
@@ -196,3 +217,107 @@ def test_central_differences_of_the_scheme_give_the_laminate_stiffness():
                          tol=0.0, max_iter=800, fixed_iter=True)["sigma_mean"]
         np.testing.assert_allclose((sp - sm) / (2 * d), C[:, c], rtol=1e-7,
                                    atol=1e-7 * np.abs(C).max())
+
+
+UNIAXIAL = 0b111110    # every component but xx stress-controlled
+
+
+def test_uniaxial_stress_homogeneous_gives_young_and_poisson():
+    """Mixed boundary conditions, eps_xx prescribed and every other mean
+    stress zero: a homogeneous elastic cell returns sigma_xx = E eps_xx and
+    the lateral contraction -nu eps_xx (for any reference medium)."""
+    N = 6
+    Ey, nu = 2500.0, 0.35
+    e = 1e-3
+    z = np.zeros((6, N ** 3))
+    r = oms.ms_step(z, z, np.zeros(N ** 3, np.uint8), [ELASTIC(Ey, nu)], (N, N, N),
+                    [e, 0, 0, 0, 0, 0], np.zeros(6), 0.1, lam0=900.0, mu0=700.0, tol=1e-13,
+                    max_iter=500, stress_mask=UNIAXIAL)
+    np.testing.assert_allclose(r["E"], [e, -nu * e, -nu * e, 0, 0, 0], rtol=1e-11, atol=1e-17)
+    np.testing.assert_allclose(r["sigma_mean"], [Ey * e, 0, 0, 0, 0, 0], atol=1e-11 * Ey * e)
+
+
+def _laminate_stiffness(ph, fr):
+    """Exact effective stiffness (6x6, engineering Voigt) of a laminate with
+    layers normal to x, column by column from the exact mean stress."""
+    return np.stack([laminate_sigma(ph, fr, np.eye(6)[j]) for j in range(6)], axis=1)
+
+
+@pytest.mark.parametrize("mask", [UNIAXIAL, 0b011010])
+def test_mixed_conditions_on_a_laminate(mask):
+    """A laminate under mixed conditions reaches the state that the exact
+    effective stiffness gives for the same mixed problem, solved directly."""
+    nz, ny, nx = 4, 4, 16
+    ph = [ELASTIC(2500.0, 0.35), ELASTIC(72000.0, 0.22)]
+    layer = (np.arange(nx) >= 11).astype(np.uint8)
+    phase = np.broadcast_to(layer[None, None, :], (nz, ny, nx)).reshape(-1).copy()
+    Ebar = np.array([1e-3, 3e-4, -2e-4, 4e-4, -5e-4, 6e-4])
+    Sbar = np.array([0.0, 2.0, -1.0, 0.5, 0.0, -0.7])
+    z = np.zeros((6, phase.size))
+    r = oms.ms_step(z, z, phase, ph, (nz, ny, nx), Ebar, np.zeros(6), 0.1, tol=1e-12,
+                    max_iter=5000, stress_mask=mask, S_macro=Sbar)
+    Ceff = _laminate_stiffness(ph, [11 / 16, 5 / 16])
+    S = np.array([bool(mask >> c & 1) for c in range(6)])
+    Eref = Ebar.copy()
+    Eref[S] = np.linalg.solve(Ceff[np.ix_(S, S)], Sbar[S] - Ceff[np.ix_(S, ~S)] @ Ebar[~S])
+    sref = Ceff @ Eref
+    np.testing.assert_allclose(r["E"], Eref, rtol=1e-8, atol=1e-8 * np.abs(Eref).max())
+    np.testing.assert_allclose(r["sigma_mean"], sref, rtol=1e-8, atol=1e-8 * np.abs(sref).max())
+    np.testing.assert_allclose(r["sigma_mean"][S], Sbar[S], atol=1e-8 * np.abs(sref).max())
+
+
+def test_isotropic_part_of_stiffnesses():
+    """The isotropic part returns the Lame constants of an isotropic
+    stiffness, and for an anisotropic one it is the closest isotropic tensor
+    in the Frobenius norm of the full fourth-order tensors."""
+    lam, mu = oms.isotropic_part(np.stack([oms.voigt_stiffness(40.0, 21.0).ravel(),
+                                           oms.voigt_stiffness(-3.0, 7.5).ravel()], axis=1))
+    np.testing.assert_allclose(lam, [40.0, -3.0], rtol=1e-14)
+    np.testing.assert_allclose(mu, [21.0, 7.5], rtol=1e-14)
+    rng = np.random.default_rng(3)
+    A = rng.normal(size=(6, 6))
+    C = A @ A.T + 6 * np.eye(6)
+    l0, m0 = oms.isotropic_part(C.reshape(36, 1))
+
+    def dist(l, m):
+        return np.sum((oms.full_tensor(C.reshape(36, 1)) -
+                       oms.full_tensor(oms.voigt_stiffness(l, m).reshape(36, 1))) ** 2)
+    d0 = dist(l0[0], m0[0])
+    for dl, dm in [(1e-3, 0), (-1e-3, 0), (0, 1e-3), (0, -1e-3), (1e-3, -1e-3)]:
+        assert dist(l0[0] + dl, m0[0] + dm) > d0
+
+
+def test_reference_update_elastic_equals_fixed_rule():
+    """On an elastic field the tangent-based reference equals the fixed
+    reference from the elastic constants."""
+    N = 8
+    phase = inputs.sphere_phase(N, seed=5, radius=2.0, vol_frac=0.2)
+    ph = [ELASTIC(2500.0, 0.35), ELASTIC(72000.0, 0.22)]
+    z = np.zeros((6, N ** 3))
+    r = oms.ms_step(z, z, phase, ph, (N, N, N), [1e-3, 0, 0, 0, 0, 0], np.zeros(6), 0.1,
+                    tol=1e-8, ref_update=True)
+    np.testing.assert_allclose([r["lam0"], r["mu0"]], oms.reference_medium(ph), rtol=1e-13)
+
+
+def test_reference_update_same_solution_fewer_iterations():
+    """With a flowing matrix the tangent-based reference is softer; the
+    converged state does not depend on the reference (up to the tolerance),
+    and the softer reference needs fewer iterations."""
+    N = 8
+    phase = inputs.sphere_phase(N, seed=6, radius=2.0, vol_frac=0.2)
+    ph = inputs.paper_phases()
+    z = np.zeros((6, N ** 3))
+    E1 = np.array([4e-3, 0, 0, 0, 0, 0])
+    r1 = oms.ms_step(z, z, phase, ph, (N, N, N), E1, np.zeros(6), 1.0, tol=1e-10,
+                     stress_mask=UNIAXIAL)
+    runs = {}
+    for upd in (False, True):
+        runs[upd] = oms.ms_step(r1["eps"], r1["a"], phase, ph, (N, N, N), 2 * E1, r1["E"], 1.0,
+                                tol=1e-10, stress_mask=UNIAXIAL, ref_update=upd)
+    f, u = runs[False], runs[True]
+    assert u["mu0"] < 0.9 * f["mu0"]
+    assert u["iters"] < f["iters"]
+    scale = np.abs(f["sigma"]).max()
+    assert np.abs(u["sigma"] - f["sigma"]).max() <= 1e-7 * scale
+    np.testing.assert_allclose(u["E"], f["E"], rtol=1e-7)
+    assert abs(f["sigma_mean"][1:]).max() <= 1e-8 * abs(f["sigma_mean"][0])
