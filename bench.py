@@ -141,6 +141,52 @@ def ms_bench(steps, N=128, h=0.1, tol=1e-6):
             "sweep_updates_per_s": total * n / wall, "sigma_mean_last": mean}
 
 
+def ms_tc_bench(steps, N=150, tol=1e-6):
+    """The paper's example test: the basic scheme on a synthetic
+    metal-matrix composite (fibres 10.2 %, aspect 15) with the paper's
+    phase parameters, uniaxial tension-compression under mixed boundary
+    conditions (eps_xx prescribed, all other mean stresses zero), the
+    reference stiffness fixed or adjusted to the tangent field every step."""
+    import torch
+    from paper_2006_04391_amd import api, inputs
+    phase_np = inputs.mmc_phase(N, seed=4)
+    phase = torch.from_numpy(phase_np).cuda()
+    n = N ** 3
+    h, path = inputs.tension_compression_path(steps)
+    out = {"workload": f"Moulinec-Suquet basic scheme, {N}^3 synthetic metal-matrix composite "
+                       f"(fibres {phase_np.mean() * 100:.1f} %, aspect 15, r = 2.5), paper's "
+                       f"parameters, uniaxial tension-compression 0 -> 3.58454e-3 -> -3.48441e-3 "
+                       f"at 1.4e-3/s, mixed conditions, {steps} steps of h = {h:.5f} s, tol {tol}"}
+    for upd in (True, False):
+        ms = api.MS((N, N, N), inputs.paper_phases(), tol=tol, max_iter=5000, ref_update=upd)
+        eps = torch.zeros((6, n), dtype=torch.float64, device="cuda")
+        a = torch.zeros_like(eps)
+        ms.step_mixed(phase, [0.0] * 6, h, eps, a, 0b111110)   # warm-up (plans, modules)
+        eps.zero_()
+        a.zero_()
+        ms.set_macro([0.0] * 6)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters, curve = [], []
+        for e in path:
+            mean, Er, it, _ = ms.step_mixed(phase, [e, 0, 0, 0, 0, 0], h, eps, a, 0b111110)
+            iters.append(it)
+            curve.append((e, mean[0]))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms.close()
+        total = sum(iters)
+        key = "reference_update" if upd else "reference_fixed"
+        out[key] = {"wall_s": wall, "iterations_total": total, "iterations": iters,
+                    "ms_per_iteration": wall / total * 1e3,
+                    "sweep_updates_per_s": total * n / wall,
+                    "stress_strain": curve[:: max(1, steps // 16)] + [curve[-1]]}
+        log(f"[bench] MS tension-compression {N}^3 ({key}): {steps} steps, {total} iterations, "
+            f"{wall:.2f} s, {wall / total * 1e3:.3f} ms/iteration")
+        del eps, a
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -155,6 +201,8 @@ def main():
                     help="host processes generating the requests' microstructures")
     ap.add_argument("--ms-steps", type=int, default=20,
                     help="load steps of the 128^3 Moulinec-Suquet run (0 skips it)")
+    ap.add_argument("--tc-steps", type=int, default=80,
+                    help="load steps of the 150^3 tension-compression test (0 skips it)")
     ap.add_argument("--no-rk23", action="store_true", help="skip the adaptive ode23 and ode12 legs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (known traffic: 1 GiB read, "
@@ -298,6 +346,8 @@ def main():
 
     if args.ms_steps > 0:
         out["ms"] = ms_bench(args.ms_steps)
+    if args.tc_steps > 0:
+        out["ms_tension_compression"] = ms_tc_bench(args.tc_steps)
 
     if serve_reqs is not None:
         from paper_2006_04391_amd import serve

@@ -163,7 +163,17 @@ int32_t automat_evaluate_backward(int64_t n, const double *eps_new, const double
  * reference medium C0 = (lambda0, mu0); Green operator
  * Gamma0(xi) = [d_ki q_h q_j + d_hi q_k q_j + d_kj q_h q_i + d_hj q_k q_i]/(4 mu0)
  *              - (lambda0 + mu0)/(mu0 (lambda0 + 2 mu0)) q_i q_j q_k q_h,
- * q = xi/|xi|, at every non-zero frequency; the zero frequency carries E.
+ * q = xi/|xi|, at every non-zero frequency except where a Nyquist index
+ * N/2 of an even dimension meets another non-zero component (+N/2 and -N/2
+ * are one index there but different directions): there Gamma0 = C0^-1, so
+ * the converged stress has no content at those frequencies and the
+ * converged fields do not depend on C0. The zero frequency carries the
+ * macroscopic strain. Mixed boundary conditions (the paper's Section
+ * "Example", paragraph "Boundary Conditions": a uniaxial
+ * tension-compression test) prescribe the mean stress on a chosen set of
+ * components and the mean strain on the rest; the reference stiffness is
+ * fixed or adjusted to the tangent field at the start of every load step
+ * (paragraph "Material Law Evaluations").
  * ------------------------------------------------------------------------ */
 typedef struct automat_ms automat_ms; /* opaque; owns hipFFT plans and work buffers */
 
@@ -176,7 +186,15 @@ typedef struct automat_ms_options {
                                 and largest Lame constants of the phases */
     double newton_tol;       /* per-point Newton tolerance, > 0 */
     int32_t newton_max_iter; /* per-point Newton update limit, >= 1 */
-    int32_t reserved;
+    int32_t ref_update;      /* 1: at the start of every load step, after the initial
+                                guess, one sweep with tangent sets C0 to the means of
+                                the smallest and largest Lame constants of the isotropic
+                                parts of the tangents (lambda = K - 2 mu / 3 with
+                                3K = sum of the normal block / 3 and
+                                10 mu = C11 + C22 + C33 + 2 (C44 + C55 + C66) - 3K);
+                                the reference then stays in use until the next update
+                                (automat_ms_reference reports it). 0: fixed. Needs
+                                36 more doubles per voxel (allocated on the first step) */
 } automat_ms_options;
 
 /* Create a solver for an nx * ny * nz grid (each >= 2). params and opts are
@@ -198,6 +216,28 @@ int32_t automat_ms_create(int32_t nx, int32_t ny, int32_t nz, const automat_para
 int32_t automat_ms_step(automat_ms *ms, const uint8_t *phase, const double *E_macro, double h,
                         double *eps, double *a, double *sigma_out, double *sigma_mean,
                         int32_t *iters, double *residual, void *stream);
+
+/* One load step under mixed boundary conditions. Bit c of stress_mask
+ * (0 <= stress_mask < 64, components in engineering Voigt order 11 22 33 23
+ * 13 12) selects a stress-controlled component, whose mean stress is
+ * S_macro[c] (host [6], or NULL for zero targets); the other components
+ * have the mean strain E_macro[c] (host [6]; stress-controlled entries are
+ * ignored). Every update sets the zero frequency to the macroscopic strain
+ * E that solves mean(tau) + C0 E = S_macro on the stress-controlled set
+ * (closed form for the isotropic C0), so at convergence the mean stress
+ * meets the targets. The initial guess shifts the previous field by the
+ * prescribed strain increments and, on stress-controlled components, by
+ * the increments that keep the reference medium's stress there unchanged.
+ * E_reached (host [6], or NULL) receives the macroscopic strain of the last
+ * update, and the next step starts from it. The convergence test divides by
+ * the norm of that strain. Other arguments, synchronization and errors as
+ * automat_ms_step (AUTOMAT_EINVAL also for an adjusted reference that is
+ * not positive definite). The reverse step (automat_ms_adjoint_step)
+ * covers strain-controlled steps only. */
+int32_t automat_ms_step_mixed(automat_ms *ms, const uint8_t *phase, const double *E_macro,
+                              const double *S_macro, uint32_t stress_mask, double h, double *eps,
+                              double *a, double *sigma_out, double *sigma_mean, double *E_reached,
+                              int32_t *iters, double *residual, void *stream);
 
 /* Set the macroscopic strain the next step starts from (e.g. after loading
  * a checkpointed strain field). */

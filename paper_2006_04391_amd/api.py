@@ -173,7 +173,7 @@ class MS:
     automat_ms_* entry points). shape = (nz, ny, nx), x fastest."""
 
     def __init__(self, shape, phases, *, tol=1e-6, max_iter=1000, fixed_iter=False, lambda0=0.0,
-                 mu0=0.0, newton_tol=1e-12, newton_max_iter=50, device=None):
+                 mu0=0.0, newton_tol=1e-12, newton_max_iter=50, ref_update=False, device=None):
         if isinstance(shape, int):
             shape = (shape, shape, shape)
         self.shape = tuple(int(s) for s in shape)
@@ -190,6 +190,7 @@ class MS:
         opts.mu0 = float(mu0)
         opts.newton_tol = float(newton_tol)
         opts.newton_max_iter = int(newton_max_iter)
+        opts.ref_update = 1 if ref_update else 0
         self._opts = opts
         self._h = ctypes.c_void_p()
         lib = load()
@@ -228,6 +229,31 @@ class MS:
                                         ctypes.byref(res), _stream(dev))
         check("automat_ms_step", rc)
         return list(mean), iters.value, res.value
+
+    def step_mixed(self, phase, E_macro, h, eps, a, stress_mask, S_macro=None, sigma_out=None):
+        """Advance one load step under mixed conditions (automat_ms_step_mixed):
+        bit c of stress_mask makes component c stress-controlled with mean
+        stress S_macro[c] (zero if None). Returns (sigma_mean (6,), E reached
+        (6,), iterations, last relative strain change)."""
+        dev = self.device
+        eps = _field(eps, "eps", 6, self.n, dev)
+        a = _field(a, "a", 6, self.n, dev)
+        phase = _phase_ids(phase, self.n, dev)
+        if sigma_out is not None:
+            sigma_out = _field(sigma_out, "sigma_out", 6, self.n, dev)
+        E = (ctypes.c_double * 6)(*[float(x) for x in E_macro])
+        S = (ctypes.c_double * 6)(*[float(x) for x in S_macro]) if S_macro is not None else None
+        mean = (ctypes.c_double * 6)()
+        Er = (ctypes.c_double * 6)()
+        iters = ctypes.c_int32()
+        res = ctypes.c_double()
+        with torch.cuda.device(dev):
+            rc = load().automat_ms_step_mixed(self._h, _ptr(phase), E, S, int(stress_mask),
+                                              float(h), _ptr(eps), _ptr(a), _ptr(sigma_out), mean,
+                                              Er, ctypes.byref(iters), ctypes.byref(res),
+                                              _stream(dev))
+        check("automat_ms_step_mixed", rc)
+        return list(mean), list(Er), iters.value, res.value
 
     def adjoint_step(self, phase, h, eps, a_prev, a_next, w=None, grad_sigma=None, grad_a=None,
                      grad_a_prev=None, grad_params=None):

@@ -3,9 +3,8 @@
 // "Example", paragraph "Material Law Evaluations": one material sweep
 // without tangent per fixed-point iteration).
 //
-// Periodic grid of nx * ny * nz voxels (x fastest), strain-controlled load
-// with macroscopic strain E per step. With an isotropic reference medium
-// C0 = (lambda0, mu0), one iteration is
+// Periodic grid of nx * ny * nz voxels (x fastest). With an isotropic
+// reference medium C0 = (lambda0, mu0), one iteration is
 //
 //   tau     = material(eps, a_n) - C0 eps              (one evaluation sweep
 //                                                       writing the polarization)
@@ -16,9 +15,23 @@
 //
 // with Gamma0_khij = [d_ki q_h q_j + d_hi q_k q_j + d_kj q_h q_i +
 // d_hj q_k q_i] / (4 mu0) - (lambda0 + mu0) / (mu0 (lambda0 + 2 mu0))
-// q_i q_j q_k q_h, q = xi / |xi| (continuous operator at every xi != 0,
-// including the Nyquist planes), applied as
+// q_i q_j q_k q_h, q = xi / |xi|, applied as
 // eps^_kh = -[(q_k v_h + q_h v_k) / (2 mu0) - c2 (q.v) q_k q_h], v = tau^ q.
+// Where a Nyquist index N/2 of an even dimension meets another non-zero
+// component, +N/2 and -N/2 are one index but different directions; there
+// Gamma0 is the reference compliance C0^-1, so the converged stress has no
+// content at those frequencies and the fixed point does not depend on C0.
+//
+// Mixed boundary conditions (the paper's uniaxial tension-compression test):
+// components in the stress-controlled set take the macroscopic stress
+// S_bar, the others the macroscopic strain E_bar; the zero frequency of
+// every update is the E that makes the reference medium's mean stress meet
+// the targets, mean(tau) + C0 E = S_bar on the stress-controlled set, solved
+// in closed form on the device from tau^(0) = n mean(tau).
+// Reference update (the paper's per-load-step reference stiffness): a sweep
+// with tangent at the step's initial guess; C0 takes the means of the
+// smallest and largest Lame constants of the isotropic parts of the tangents
+// (3K = C:(I x I)/3 over the normal block, 10 mu = C_ijij - 3K).
 // Norms are tensor norms (engineering shears count half their square), the
 // L2 norm of a field is averaged over voxels. At convergence one more sweep
 // at the converged strain gives the committed a_{n+1} and sigma.
@@ -46,6 +59,39 @@ struct MsField {
 };
 
 __device__ __forceinline__ double freq(int k, int N) { return (double)(k <= N / 2 ? k : k - N) / N; }
+
+// Zero-frequency data of one update: the prescribed strain (E) and stress
+// (S) and the stress-controlled set (bit c of mask); Eout receives the
+// macroscopic strain of the update (device).
+struct MacroBC {
+    double E[6], S[6];
+    uint32_t mask;
+    double *Eout;
+};
+
+// E with E_c = Ebar_c off the stress-controlled set and
+// (C0 E)_c = r_c on it, for the isotropic C0 = (lam, mu) in engineering
+// Voigt form. Shears decouple (mu E_c = r_c); the m stress-controlled
+// normal components x_i solve lam (K + X) + 2 mu x_i = r_i with K the sum of
+// the prescribed normal strains and X = sum x_i, so
+// X = (sum r_i - m lam K) / (m lam + 2 mu).
+__host__ __device__ inline void mixed_solve(double lam, double mu, uint32_t mask,
+                                            const double *Ebar, const double *r, double *E) {
+    double K = 0.0, R = 0.0;
+    int m = 0;
+    for (int c = 0; c < 3; ++c) {
+        if (mask >> c & 1u) {
+            ++m;
+            R += r[c];
+        } else {
+            K += Ebar[c];
+        }
+    }
+    const double X = m ? (R - m * lam * K) / (m * lam + 2.0 * mu) : 0.0;
+    for (int c = 0; c < 3; ++c)
+        E[c] = (mask >> c & 1u) ? (r[c] - lam * (K + X)) / (2.0 * mu) : Ebar[c];
+    for (int c = 3; c < 6; ++c) E[c] = (mask >> c & 1u) ? r[c] / mu : Ebar[c];
+}
 
 // accumulate -Gamma0(q) : t for a (not necessarily unit) frequency q
 __device__ __forceinline__ void gamma_add(double q1, double q2, double q3,
@@ -75,13 +121,10 @@ __device__ __forceinline__ void gamma_add(double q1, double q2, double q3,
     }
 }
 
-// eps^ = -Gamma0 : tau^ on the half spectrum (in place); eps^(0) = E * n.
-// A component k = N/2 of an even dimension stands for both +N/2 and -N/2:
-// the operator is averaged over those sign choices, which keeps the
-// spectrum Hermitian (and is the continuous operator on the pure Nyquist
-// axes, Gamma0 being even in xi).
-__global__ void gamma_kernel(hipfftDoubleComplex *spec, MsField f, double c1, double c2,
-                             double E0, double E1, double E2, double E3, double E4, double E5) {
+// eps^ = -Gamma0 : tau^ on the half spectrum (in place); eps^(0) = E * n
+// with E from the macroscopic conditions (above).
+__global__ void gamma_kernel(hipfftDoubleComplex *spec, MsField f, double lam0, double mu0,
+                             MacroBC bc) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= f.nh) return;
     const int nxh = f.nx / 2 + 1;
@@ -91,31 +134,44 @@ __global__ void gamma_kernel(hipfftDoubleComplex *spec, MsField f, double c1, do
     const int64_t s = f.nh;
     if (kx == 0 && ky == 0 && kz == 0) {
         const double nn = (double)f.n;
-        const double E[6] = {E0, E1, E2, E3, E4, E5};
+        double r[6], E[6];
+        for (int c = 0; c < 6; ++c) r[c] = bc.S[c] - spec[c * s].x / nn;
+        mixed_solve(lam0, mu0, bc.mask, bc.E, r, E);
         for (int c = 0; c < 6; ++c) {
             spec[c * s].x = E[c] * nn;
             spec[c * s].y = 0.0;
+            if (bc.Eout) bc.Eout[c] = E[c];
         }
         return;
     }
-    const double q1 = freq(kx, f.nx), q2 = freq(ky, f.ny), q3 = freq(kz, f.nz);
     const bool n1 = (f.nx % 2 == 0) && kx == f.nx / 2;
     const bool n2 = (f.ny % 2 == 0) && ky == f.ny / 2;
     const bool n3 = (f.nz % 2 == 0) && kz == f.nz / 2;
+    const int nonzero = (kx != 0) + (ky != 0) + (kz != 0);
     hipfftDoubleComplex t[6];
     for (int c = 0; c < 6; ++c) t[c] = spec[c * s + idx];
     double er[6] = {0, 0, 0, 0, 0, 0}, ei[6] = {0, 0, 0, 0, 0, 0};
-    int cnt = 0;
-    for (int p = 0; p < 8; ++p) {
-        const double s1 = (p & 1) ? -1.0 : 1.0, s2 = (p & 2) ? -1.0 : 1.0, s3 = (p & 4) ? -1.0 : 1.0;
-        if ((s1 < 0 && !n1) || (s2 < 0 && !n2) || (s3 < 0 && !n3)) continue;
-        gamma_add(s1 * q1, s2 * q2, s3 * q3, t, c1, c2, er, ei);
-        ++cnt;
+    if ((n1 || n2 || n3) && nonzero >= 2) {
+        // -C0^-1 : t; normal strains (t_i - lam0 / (3 lam0 + 2 mu0) tr t) / (2 mu0),
+        // engineering shears t_c / mu0
+        const double g = lam0 / (3.0 * lam0 + 2.0 * mu0);
+        const double trr = t[0].x + t[1].x + t[2].x, tri = t[0].y + t[1].y + t[2].y;
+        for (int c = 0; c < 3; ++c) {
+            er[c] = -(t[c].x - g * trr) / (2.0 * mu0);
+            ei[c] = -(t[c].y - g * tri) / (2.0 * mu0);
+        }
+        for (int c = 3; c < 6; ++c) {
+            er[c] = -t[c].x / mu0;
+            ei[c] = -t[c].y / mu0;
+        }
+    } else {
+        const double c1 = 1.0 / (2.0 * mu0);
+        const double c2 = (lam0 + mu0) / (mu0 * (lam0 + 2.0 * mu0));
+        gamma_add(freq(kx, f.nx), freq(ky, f.ny), freq(kz, f.nz), t, c1, c2, er, ei);
     }
-    const double w = 1.0 / cnt;
     for (int c = 0; c < 6; ++c) {
-        spec[c * s + idx].x = er[c] * w;
-        spec[c * s + idx].y = ei[c] * w;
+        spec[c * s + idx].x = er[c];
+        spec[c * s + idx].y = ei[c];
     }
 }
 
@@ -176,6 +232,62 @@ __global__ __launch_bounds__(kRedBlock) void finish_kernel(const double *partial
     __syncthreads();
     for (int w = kRedBlock / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+// per-block min and max of the Lame constants of the isotropic parts of a
+// tangent field [36][n] (row-major 6x6 per point): partial[4][gridDim.x] =
+// min lambda, max lambda, min mu, max mu (NaN entries are skipped)
+__global__ __launch_bounds__(kRedBlock) void iso_minmax_kernel(const double *C, int64_t n,
+                                                               double *partial) {
+    __shared__ double red[4][kRedBlock];
+    double v[4] = {INFINITY, -INFINITY, INFINITY, -INFINITY};
+    for (int64_t i = (int64_t)blockIdx.x * kRedBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kRedBlock) {
+        double k3 = 0.0;
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) k3 += C[(6 * r + c) * n + i];
+        k3 *= 1.0 / 3.0;  // 3 K
+        const double isym = C[0 * n + i] + C[7 * n + i] + C[14 * n + i] +
+                            2.0 * (C[21 * n + i] + C[28 * n + i] + C[35 * n + i]);
+        const double mu = (isym - k3) / 10.0;
+        const double lam = (k3 - 2.0 * mu) / 3.0;
+        v[0] = fmin(v[0], lam);
+        v[1] = fmax(v[1], lam);
+        v[2] = fmin(v[2], mu);
+        v[3] = fmax(v[3], mu);
+    }
+    for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int w = kRedBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int k = 0; k < 4; ++k)
+                red[k][threadIdx.x] = (k & 1) ? fmax(red[k][threadIdx.x], red[k][threadIdx.x + w])
+                                              : fmin(red[k][threadIdx.x], red[k][threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 4; ++k) partial[k * gridDim.x + blockIdx.x] = red[k][0];
+}
+
+// min (even rows) or max (odd rows) of m partials per row
+__global__ __launch_bounds__(kRedBlock) void finish_minmax_kernel(const double *partial, int m,
+                                                                  double *out) {
+    __shared__ double red[kRedBlock];
+    const bool mx = blockIdx.x & 1;
+    double s = mx ? -INFINITY : INFINITY;
+    for (int b = threadIdx.x; b < m; b += kRedBlock) {
+        const double x = partial[blockIdx.x * m + b];
+        s = mx ? fmax(s, x) : fmin(s, x);
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kRedBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            red[threadIdx.x] = mx ? fmax(red[threadIdx.x], red[threadIdx.x + w])
+                                  : fmin(red[threadIdx.x], red[threadIdx.x + w]);
         __syncthreads();
     }
     if (threadIdx.x == 0) out[blockIdx.x] = red[0];
@@ -276,8 +388,8 @@ struct automat_ms {
     double *sig;   // [6][n] stress / polarization / raw inverse FFT output
     hipfftDoubleComplex *spec;  // [6][nh]
     double *partial;            // [6 * kRedBlocks]
-    double *scal;               // [8] reduced scalars
-    double *host_scal;          // pinned [8]
+    double *scal;               // [16] reduced scalars; [8..13] the macro strain
+    double *host_scal;          // pinned [16]
     // reverse step work space, allocated on first use
     double *tan;                // [36][n] consistent tangent at the converged strain
     double *lam;                // [6][n] adjoint field
@@ -288,6 +400,7 @@ struct automat_ms {
 static int32_t ms_check_opts(const automat_ms_options *o) {
     if (!o) return AUTOMAT_EINVAL;
     if (o->max_iter < 1 || o->newton_max_iter < 1) return AUTOMAT_EINVAL;
+    if (o->ref_update != 0 && o->ref_update != 1) return AUTOMAT_EINVAL;
     if (!o->fixed_iter && !(o->tol > 0.0)) return AUTOMAT_EINVAL;
     if (!(o->newton_tol > 0.0)) return AUTOMAT_EINVAL;
     return AUTOMAT_OK;
@@ -337,8 +450,8 @@ extern "C" int32_t automat_ms_create(int32_t nx, int32_t ny, int32_t nz,
     bool ok = hipMalloc(&m->sig, nb) == hipSuccess &&
               hipMalloc(&m->spec, nc) == hipSuccess &&
               hipMalloc(&m->partial, 6 * kRedBlocks * sizeof(double)) == hipSuccess &&
-              hipMalloc(&m->scal, 8 * sizeof(double)) == hipSuccess &&
-              hipHostMalloc(&m->host_scal, 8 * sizeof(double), hipHostMallocDefault) == hipSuccess;
+              hipMalloc(&m->scal, 16 * sizeof(double)) == hipSuccess &&
+              hipHostMalloc(&m->host_scal, 16 * sizeof(double), hipHostMallocDefault) == hipSuccess;
     ok = ok && hipfftPlanMany(&m->fwd, 3, dims, dims, 1, (int)m->f.n, dims_c, 1, (int)m->f.nh,
                               HIPFFT_D2Z, 6) == HIPFFT_SUCCESS;
     ok = ok && hipfftPlanMany(&m->inv, 3, dims, dims_c, 1, (int)m->f.nh, dims, 1, (int)m->f.n,
@@ -380,62 +493,117 @@ static double tensor_norm(const double *e) {
                 0.5 * (e[3] * e[3] + e[4] * e[4] + e[5] * e[5]));
 }
 
-extern "C" int32_t automat_ms_step(automat_ms *m, const uint8_t *phase, const double *E_macro,
-                                   double h, double *eps, double *a, double *sigma_out,
-                                   double *sigma_mean, int32_t *iters, double *residual,
-                                   void *stream) {
+static int32_t ensure_buffer(double **p, size_t bytes) {
+    if (*p) return AUTOMAT_OK;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return AUTOMAT_ENOMEM;
+    }
+    return AUTOMAT_OK;
+}
+
+static int32_t read_scalars(automat_ms *m, int count, hipStream_t s) {
+    if (hipMemcpyAsync(m->host_scal, m->scal, count * sizeof(double), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return AUTOMAT_EHIP;
+    return AUTOMAT_OK;
+}
+
+// C0 from the tangent field at the current strain (a_n fixed): the means of
+// the extreme Lame constants of the isotropic parts
+static int32_t update_reference(automat_ms *m, const uint8_t *phase, double h, const double *eps,
+                                const double *a, hipStream_t s, int rb) {
+    const int64_t n = m->f.n;
+    int32_t rc = ensure_buffer(&m->tan, (size_t)n * 36 * sizeof(double));
+    if (rc) return rc;
+    rc = automat_evaluate_ex(n, eps, a, phase, &m->params, h, m->opts.newton_tol,
+                             m->opts.newton_max_iter, m->sig, nullptr, m->tan, nullptr, nullptr,
+                             0u, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(iso_minmax_kernel, dim3(rb), dim3(kRedBlock), 0, s, m->tan, n, m->partial);
+    hipLaunchKernelGGL(finish_minmax_kernel, dim3(4), dim3(kRedBlock), 0, s, m->partial, rb,
+                       m->scal);
+    rc = read_scalars(m, 4, s);
+    if (rc) return rc;
+    const double lam0 = 0.5 * (m->host_scal[0] + m->host_scal[1]);
+    const double mu0 = 0.5 * (m->host_scal[2] + m->host_scal[3]);
+    if (!std::isfinite(lam0) || !(mu0 > 0.0) || !(lam0 + 2.0 * mu0 / 3.0 > 0.0))
+        return AUTOMAT_EINVAL;
+    m->lam0 = lam0;
+    m->mu0 = mu0;
+    return AUTOMAT_OK;
+}
+
+extern "C" int32_t automat_ms_step_mixed(automat_ms *m, const uint8_t *phase,
+                                         const double *E_macro, const double *S_macro,
+                                         uint32_t stress_mask, double h, double *eps, double *a,
+                                         double *sigma_out, double *sigma_mean,
+                                         double *E_reached, int32_t *iters, double *residual,
+                                         void *stream) {
     if (!m || !phase || !E_macro || !eps || !a) return AUTOMAT_EINVAL;
-    if (!std::isfinite(h) || !(h > 0.0)) return AUTOMAT_EINVAL;
+    if (!std::isfinite(h) || !(h > 0.0) || stress_mask > 63u) return AUTOMAT_EINVAL;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int64_t n = m->f.n;
     const int tb = 256;
     const int gb = (int)((n + tb - 1) / tb);
     if (hipfftSetStream(m->fwd, s) != HIPFFT_SUCCESS || hipfftSetStream(m->inv, s) != HIPFFT_SUCCESS)
         return AUTOMAT_EHIP;
-    // initial guess: previous strain field shifted by the macro increment
-    double d[6];
-    for (int c = 0; c < 6; ++c) d[c] = E_macro[c] - m->E_prev[c];
-    hipLaunchKernelGGL(shift_kernel, dim3(gb), dim3(tb), 0, s, eps, n, d[0], d[1], d[2], d[3],
-                       d[4], d[5]);
-    const double En = fmax(tensor_norm(E_macro), 1e-300);
-    const double c1 = 1.0 / (2.0 * m->mu0);
-    const double c2 = (m->lam0 + m->mu0) / (m->mu0 * (m->lam0 + 2.0 * m->mu0));
+    MacroBC bc;
+    for (int c = 0; c < 6; ++c) {
+        bc.E[c] = (stress_mask >> c & 1u) ? 0.0 : E_macro[c];
+        bc.S[c] = S_macro ? S_macro[c] : 0.0;
+    }
+    bc.mask = stress_mask;
+    bc.Eout = m->scal + 8;
+    // initial guess: previous strain field shifted by the prescribed strain
+    // increments and, on stress-controlled components, the increments that
+    // keep the reference medium's stress there unchanged
+    double dE[6], d[6];  // d: prescribed increments, zero on the stress-controlled set
+    for (int c = 0; c < 6; ++c) d[c] = (stress_mask >> c & 1u) ? 0.0 : E_macro[c] - m->E_prev[c];
+    if (stress_mask) {
+        const double zero[6] = {0, 0, 0, 0, 0, 0};
+        mixed_solve(m->lam0, m->mu0, stress_mask, d, zero, dE);
+    } else {
+        for (int c = 0; c < 6; ++c) dE[c] = d[c];
+    }
+    hipLaunchKernelGGL(shift_kernel, dim3(gb), dim3(tb), 0, s, eps, n, dE[0], dE[1], dE[2], dE[3],
+                       dE[4], dE[5]);
+    double Ecur[6];
+    for (int c = 0; c < 6; ++c) Ecur[c] = m->E_prev[c] + dE[c];
     const int nhb = (int)((m->f.nh + tb - 1) / tb);
     const int rb = (int)((n + kRedBlock - 1) / kRedBlock) < kRedBlocks
                        ? (int)((n + kRedBlock - 1) / kRedBlock)
                        : kRedBlocks;
+    int32_t rc = AUTOMAT_OK;
+    if (m->opts.ref_update) {
+        rc = update_reference(m, phase, h, eps, a, s, rb);
+        if (rc) return rc;
+    }
     int it = 0;
     double err = 0.0;
-    int32_t rc = AUTOMAT_OK;
     for (it = 1; it <= m->opts.max_iter; ++it) {
         // material sweep writing the polarization tau = sigma - C0 eps
         rc = evaluate_polarized(n, eps, a, phase, &m->params, h, m->opts.newton_tol,
                                 m->opts.newton_max_iter, m->lam0, m->mu0, m->sig, stream);
         if (rc) return rc;
         if (hipfftExecD2Z(m->fwd, m->sig, m->spec) != HIPFFT_SUCCESS) return AUTOMAT_EHIP;
-        hipLaunchKernelGGL(gamma_kernel, dim3(nhb), dim3(tb), 0, s, m->spec, m->f, c1, c2,
-                           E_macro[0], E_macro[1], E_macro[2], E_macro[3], E_macro[4], E_macro[5]);
+        hipLaunchKernelGGL(gamma_kernel, dim3(nhb), dim3(tb), 0, s, m->spec, m->f, m->lam0,
+                           m->mu0, bc);
         if (hipfftExecZ2D(m->inv, m->spec, m->sig) != HIPFFT_SUCCESS) return AUTOMAT_EHIP;
         hipLaunchKernelGGL(update_kernel, dim3(rb), dim3(kRedBlock), 0, s, eps, m->sig, n,
                            m->partial);
         hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedBlock), 0, s, m->partial, rb, m->scal);
-        if (!m->opts.fixed_iter) {
-            if (hipMemcpyAsync(m->host_scal, m->scal, sizeof(double), hipMemcpyDeviceToHost, s) !=
-                    hipSuccess ||
-                hipStreamSynchronize(s) != hipSuccess)
-                return AUTOMAT_EHIP;
-            err = sqrt(m->host_scal[0] / (double)n) / En;
-            if (err <= m->opts.tol) break;
+        if (!m->opts.fixed_iter || it == m->opts.max_iter) {
+            rc = read_scalars(m, 14, s);
+            if (rc) return rc;
+            for (int c = 0; c < 6; ++c) Ecur[c] = m->host_scal[8 + c];
+            err = sqrt(m->host_scal[0] / (double)n) / fmax(tensor_norm(Ecur), 1e-300);
+            if (!m->opts.fixed_iter && err <= m->opts.tol) break;
         }
     }
     if (it > m->opts.max_iter) it = m->opts.max_iter;
-    if (m->opts.fixed_iter) {
-        if (hipMemcpyAsync(m->host_scal, m->scal, sizeof(double), hipMemcpyDeviceToHost, s) !=
-                hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
-            return AUTOMAT_EHIP;
-        err = sqrt(m->host_scal[0] / (double)n) / En;
-    }
     // commit: sweep at the converged strain, a_n <- a_{n+1}
     double *sig = sigma_out ? sigma_out : m->sig;
     rc = automat_evaluate_ex(n, eps, a, phase, &m->params, h, m->opts.newton_tol,
@@ -445,17 +613,26 @@ extern "C" int32_t automat_ms_step(automat_ms *m, const uint8_t *phase, const do
     if (sigma_mean) {
         hipLaunchKernelGGL(mean6_kernel, dim3(rb), dim3(kRedBlock), 0, s, sig, n, m->partial);
         hipLaunchKernelGGL(finish_kernel, dim3(6), dim3(kRedBlock), 0, s, m->partial, rb, m->scal);
-        if (hipMemcpyAsync(m->host_scal, m->scal, 6 * sizeof(double), hipMemcpyDeviceToHost, s) !=
-                hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
-            return AUTOMAT_EHIP;
+        rc = read_scalars(m, 6, s);
+        if (rc) return rc;
         for (int c = 0; c < 6; ++c) sigma_mean[c] = m->host_scal[c] / (double)n;
     }
-    for (int c = 0; c < 6; ++c) m->E_prev[c] = E_macro[c];
+    for (int c = 0; c < 6; ++c) {
+        m->E_prev[c] = Ecur[c];
+        if (E_reached) E_reached[c] = Ecur[c];
+    }
     if (iters) *iters = it;
     if (residual) *residual = err;
     if (hipGetLastError() != hipSuccess) return AUTOMAT_EHIP;
     return AUTOMAT_OK;
+}
+
+extern "C" int32_t automat_ms_step(automat_ms *m, const uint8_t *phase, const double *E_macro,
+                                   double h, double *eps, double *a, double *sigma_out,
+                                   double *sigma_mean, int32_t *iters, double *residual,
+                                   void *stream) {
+    return automat_ms_step_mixed(m, phase, E_macro, nullptr, 0u, h, eps, a, sigma_out, sigma_mean,
+                                 nullptr, iters, residual, stream);
 }
 
 extern "C" int32_t automat_ms_set_macro(automat_ms *m, const double *E_prev) {
@@ -469,14 +646,14 @@ extern "C" int32_t automat_ms_set_macro(automat_ms *m, const double *E_prev) {
 static int32_t ms_gamma(automat_ms *m, const double *x, hipStream_t s) {
     const int tb = 256;
     const int nhb = (int)((m->f.nh + tb - 1) / tb);
-    const double c1 = 1.0 / (2.0 * m->mu0);
-    const double c2 = (m->lam0 + m->mu0) / (m->mu0 * (m->lam0 + 2.0 * m->mu0));
+    MacroBC bc;
+    std::memset(&bc, 0, sizeof bc);  // zero mean: eps^(0) = 0
     if (hipMemcpyAsync(m->sig, x, (size_t)m->f.n * 6 * sizeof(double), hipMemcpyDeviceToDevice,
                        s) != hipSuccess)
         return AUTOMAT_EHIP;
     if (hipfftExecD2Z(m->fwd, m->sig, m->spec) != HIPFFT_SUCCESS) return AUTOMAT_EHIP;
-    hipLaunchKernelGGL(gamma_kernel, dim3(nhb), dim3(tb), 0, s, m->spec, m->f, c1, c2, 0.0, 0.0,
-                       0.0, 0.0, 0.0, 0.0);
+    hipLaunchKernelGGL(gamma_kernel, dim3(nhb), dim3(tb), 0, s, m->spec, m->f, m->lam0, m->mu0,
+                       bc);
     if (hipfftExecZ2D(m->inv, m->spec, m->sig) != HIPFFT_SUCCESS) return AUTOMAT_EHIP;
     return AUTOMAT_OK;
 }
@@ -496,13 +673,9 @@ extern "C" int32_t automat_ms_adjoint_step(automat_ms *m, const uint8_t *phase, 
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int64_t n = m->f.n;
     const size_t fb = (size_t)n * 6 * sizeof(double);
-    if (!m->tan) {
-        if (hipMalloc(&m->tan, 6 * fb) != hipSuccess || hipMalloc(&m->lam, fb) != hipSuccess ||
-            hipMalloc(&m->rhs, fb) != hipSuccess || hipMalloc(&m->gs, fb) != hipSuccess) {
-            (void)hipGetLastError();
-            return AUTOMAT_ENOMEM;
-        }
-    }
+    if (ensure_buffer(&m->tan, 6 * fb) || ensure_buffer(&m->lam, fb) ||
+        ensure_buffer(&m->rhs, fb) || ensure_buffer(&m->gs, fb))
+        return AUTOMAT_ENOMEM;
     if (hipfftSetStream(m->fwd, s) != HIPFFT_SUCCESS || hipfftSetStream(m->inv, s) != HIPFFT_SUCCESS)
         return AUTOMAT_EHIP;
     const int tb = 256;

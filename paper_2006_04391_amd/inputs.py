@@ -205,6 +205,30 @@ def fibre_phase(N: int, seed: int, radius: float = 4.0, length: float = 64.0,
     return grid.reshape(-1)
 
 
+def tension_compression_path(steps: int = 80, rate: float = 1.4e-3, e_max: float = 3.58454e-3,
+                             e_min: float = -3.48441e-3):
+    """Macroscopic axial strain of a uniaxial tension-compression cycle at
+    constant absolute strain rate: 0 -> e_max -> e_min, cut into `steps`
+    equal time steps (the test of the paper's Section "Example", paragraph
+    "Boundary Conditions"; its default of 80 load steps). Returns (h, list of
+    the axial strains at the ends of the steps)."""
+    t1 = e_max / rate
+    T = t1 + (e_max - e_min) / rate
+    h = T / steps
+
+    def e(t):
+        return rate * t if t <= t1 else e_max - rate * (t - t1)
+    return h, [e(k * h) for k in range(1, steps + 1)]
+
+
+def mmc_phase(N: int = 150, seed: int = 0, vol_frac: float = 0.102, aspect: float = 15.0,
+              radius: float = 2.5) -> np.ndarray:
+    """Synthetic metal-matrix-composite microstructure standing in for the
+    paper's GeoDict volume element: straight fibres of length/diameter
+    `aspect`, isotropic directions, `vol_frac` fibre content."""
+    return fibre_phase(N, seed, radius=radius, length=2.0 * radius * aspect, vol_frac=vol_frac)
+
+
 def sphere_phase(N: int, seed: int, radius: float = 6.0, vol_frac: float = 0.20) -> np.ndarray:
     """Periodic N^3 phase field of non-overlapping spheres (phase 1).
 

@@ -113,3 +113,123 @@ def test_invalid_arguments():
         api.MS((4, 4, 4), inputs.config_phases(), tol=0.0)
     with pytest.raises(_lib.AutomatError):
         api.MS((4, 4, 4), inputs.config_phases(), max_iter=0)
+
+
+UNIAXIAL = 0b111110
+
+
+def _gpu_run_mixed(shape, phase, phases, loads, h, mask, S=None, **opts):
+    from paper_2006_04391_amd import api
+    n = shape[0] * shape[1] * shape[2]
+    ms = api.MS(shape, phases, **opts)
+    eps = torch.zeros((6, n), dtype=torch.float64, device="cuda")
+    a = torch.zeros_like(eps)
+    sig = torch.empty_like(eps)
+    ph = TT(phase)
+    out = []
+    for E in loads:
+        mean, Er, it, res = ms.step_mixed(ph, E, h, eps, a, mask, S_macro=S, sigma_out=sig)
+        torch.cuda.synchronize()
+        lam0, mu0 = ms.reference()
+        out.append(dict(eps=N(eps), a=N(a), sigma=N(sig), sigma_mean=np.array(mean),
+                        E=np.array(Er), iters=it, residual=res, lam0=lam0, mu0=mu0))
+    ms.close()
+    return out
+
+
+def _oracle_run_mixed(shape, phase, phases, loads, h, mask, S=None, **opts):
+    n = shape[0] * shape[1] * shape[2]
+    eps = np.zeros((6, n))
+    a = np.zeros((6, n))
+    prev = np.zeros(6)
+    lam0, mu0 = oms.reference_medium(phases)
+    out = []
+    for E in loads:
+        r = oms.ms_step(eps, a, phase, phases, shape, E, prev, h, lam0=lam0, mu0=mu0,
+                        stress_mask=mask, S_macro=S, **opts)
+        eps, a, prev, lam0, mu0 = r["eps"], r["a"], r["E"], r["lam0"], r["mu0"]
+        out.append(r)
+    return out
+
+
+def test_mixed_uniaxial_homogeneous():
+    Ey, nu, e = 2500.0, 0.35, 1e-3
+    r = _gpu_run_mixed((6, 6, 6), np.zeros(216, np.uint8), [ELASTIC(Ey, nu)],
+                       [[e, 0, 0, 0, 0, 0]], 0.1, UNIAXIAL, lambda0=900.0, mu0=700.0, tol=1e-13,
+                       max_iter=500)[0]
+    np.testing.assert_allclose(r["E"], [e, -nu * e, -nu * e, 0, 0, 0], rtol=1e-11, atol=1e-17)
+    np.testing.assert_allclose(r["sigma_mean"], [Ey * e, 0, 0, 0, 0, 0], atol=1e-11 * Ey * e)
+
+
+@pytest.mark.parametrize("mask", [UNIAXIAL, 0b011010])
+def test_mixed_laminate_exact(mask):
+    from tests.test_ms_oracle import _laminate_stiffness
+    nz, ny, nx = 4, 4, 16
+    ph = [ELASTIC(2500.0, 0.35), ELASTIC(72000.0, 0.22)]
+    layer = (np.arange(nx) >= 11).astype(np.uint8)
+    phase = np.broadcast_to(layer[None, None, :], (nz, ny, nx)).reshape(-1).copy()
+    Ebar = np.array([1e-3, 3e-4, -2e-4, 4e-4, -5e-4, 6e-4])
+    Sbar = np.array([0.0, 2.0, -1.0, 0.5, 0.0, -0.7])
+    r = _gpu_run_mixed((nz, ny, nx), phase, ph, [Ebar], 0.1, mask, S=Sbar, tol=1e-12,
+                       max_iter=5000)[0]
+    Ceff = _laminate_stiffness(ph, [11 / 16, 5 / 16])
+    S = np.array([bool(mask >> c & 1) for c in range(6)])
+    Eref = Ebar.copy()
+    Eref[S] = np.linalg.solve(Ceff[np.ix_(S, S)], Sbar[S] - Ceff[np.ix_(S, ~S)] @ Ebar[~S])
+    sref = Ceff @ Eref
+    np.testing.assert_allclose(r["E"], Eref, rtol=1e-8, atol=1e-8 * np.abs(Eref).max())
+    np.testing.assert_allclose(r["sigma_mean"], sref, rtol=1e-8, atol=1e-8 * np.abs(sref).max())
+
+
+@pytest.mark.parametrize("shape,upd", [((12, 12, 12), True), ((6, 10, 12), True),
+                                       ((7, 9, 10), False)])
+def test_lockstep_parity_mixed(shape, upd):
+    """Uniaxial tension then compression under mixed conditions, the
+    reference adjusted every step: fixed iteration counts on both sides,
+    fields, reached macro strains and references agree to rounding."""
+    nz, ny, nx = shape
+    rng = np.random.default_rng(9)
+    phase = (rng.random(nz * ny * nx) < 0.2).astype(np.uint8)
+    ph = inputs.paper_phases()
+    loads = [[e, 0, 0, 0, 0, 0] for e in (2e-3, 4e-3, 1e-3, -2e-3)]
+    kw = dict(max_iter=12, fixed_iter=True, ref_update=upd)
+    g = _gpu_run_mixed(shape, phase, ph, loads, 1.0, UNIAXIAL, **kw)
+    o = _oracle_run_mixed(shape, phase, ph, loads, 1.0, UNIAXIAL, tol=0.0, **kw)
+    for gs, os_ in zip(g, o):
+        assert gs["iters"] == os_["iters"] == 12
+        for key in ("eps", "a", "sigma"):
+            assert _rel(gs[key], os_[key]) <= 1e-10, key
+        np.testing.assert_allclose(gs["E"], os_["E"], rtol=1e-10, atol=1e-10 * abs(os_["E"][0]))
+        np.testing.assert_allclose([gs["lam0"], gs["mu0"]], [os_["lam0"], os_["mu0"]], rtol=1e-12)
+        np.testing.assert_allclose(gs["sigma_mean"], os_["sigma_mean"], rtol=1e-10,
+                                   atol=1e-10 * np.abs(os_["sigma_mean"]).max())
+        assert abs(gs["residual"] - os_["residual"]) <= 1e-8 * os_["residual"]
+    assert np.abs(g[-1]["a"]).max() > 0
+    if upd:
+        assert g[1]["mu0"] < 0.95 * oms.reference_medium(ph)[1]
+
+
+def test_free_running_mixed_with_reference_update():
+    N_ = 12
+    phase = inputs.fibre_phase(N_, seed=3, radius=1.0, length=10.0, vol_frac=0.102)
+    ph = inputs.paper_phases()
+    loads = [[e, 0, 0, 0, 0, 0] for e in (1.5e-3, 3e-3, 1.5e-3)]
+    tol = 1e-6
+    g = _gpu_run_mixed((N_,) * 3, phase, ph, loads, 1.0, UNIAXIAL, tol=tol, ref_update=True)
+    o = _oracle_run_mixed((N_,) * 3, phase, ph, loads, 1.0, UNIAXIAL, tol=tol, ref_update=True)
+    for gs, os_ in zip(g, o):
+        assert abs(gs["iters"] - os_["iters"]) <= 1
+        assert gs["residual"] <= tol
+        np.testing.assert_allclose(gs["sigma_mean"], os_["sigma_mean"], rtol=10 * tol,
+                                   atol=10 * tol * np.abs(os_["sigma_mean"]).max())
+        assert np.abs(gs["sigma_mean"][1:]).max() <= 1e-4 * abs(gs["sigma_mean"][0])
+
+
+def test_mixed_invalid_arguments():
+    from paper_2006_04391_amd import api, _lib
+    ms = api.MS((4, 4, 4), inputs.config_phases())
+    z = torch.zeros((6, 64), dtype=torch.float64, device="cuda")
+    with pytest.raises(_lib.AutomatError):
+        ms.step_mixed(torch.zeros(64, dtype=torch.uint8, device="cuda"), [1e-3] + [0] * 5, 0.1,
+                      z, z.clone(), 64)
+    ms.close()
