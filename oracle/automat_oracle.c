@@ -31,8 +31,12 @@
  * dF/dDelta = I + h Psi''(A) K, K = d^2 omega / d a^2 = C + 2/3 Hm.
  *
  * Readings of the paper where it is silent (each also listed in the design
- * notes): increment unknown Delta; stop when ||F||_inf <= tol ||Delta||_inf
- * after at least one update, or when F vanishes exactly; optional stress
+ * notes): increment unknown Delta; stop when
+ * ||F||_inf <= max(tol ||Delta||_inf, 16 u ||eps - a_n||_inf), u = 2^-52:
+ * relative to the increment, or at the rounding level of the trial elastic
+ * strain that F is computed from (for a flow just above the yield stress
+ * the increment is so small that the relative test asks for more digits
+ * than F carries); optional stress
  * criterion ||C F||_inf <= tol ||sigma||_inf (the paper's suggestion to
  * converge sigma instead of a); Armijo backtracking on the convex merit
  * function Phi(Delta) = 1/2 Delta^T K Delta + h Psi(A(Delta)), whose gradient
@@ -321,6 +325,9 @@ static int eval_point(const phase_t *ph, int nph, int pid, const double eps[6],
     }
 
     double D[6] = {0, 0, 0, 0, 0, 0};
+    double floor_F = 0.0; /* 16 u ||eps - a_n||_inf */
+    for (int i = 0; i < 6; ++i) floor_F = fmax(floor_F, fabs(eps[i] - an[i]));
+    floor_F *= 16.0 * 0x1p-52;
     resid_t cur, trial;
     residual(p, C, K, eps, an, D, h, &cur);
     int k = 0, status = -1;
@@ -332,21 +339,20 @@ static int eval_point(const phase_t *ph, int nph, int pid, const double eps[6],
             status = k;
             break;
         }
-        if (k >= 1) {
-            int conv;
-            if (flags & ORACLE_SIGMA_CRITERION) {
+        if (flags & ORACLE_SIGMA_CRITERION) {
+            if (k >= 1) {
                 double CF[6], s[6], e[6];
                 matvec(C, cur.F, CF);
                 for (int i = 0; i < 6; ++i) e[i] = eps[i] - an[i] - D[i];
                 matvec(C, e, s);
-                conv = norm_inf(CF) <= tol * norm_inf(s);
-            } else {
-                conv = norm_inf(cur.F) <= tol * norm_inf(D);
+                if (norm_inf(CF) <= tol * norm_inf(s)) {
+                    status = k;
+                    break;
+                }
             }
-            if (conv) {
-                status = k;
-                break;
-            }
+        } else if (norm_inf(cur.F) <= fmax(tol * norm_inf(D), floor_F)) {
+            status = k;
+            break;
         }
         if (k >= max_iter) break;
         /* Newton step: (I + h Psi'' K) delta = F */
