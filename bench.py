@@ -36,10 +36,10 @@ BYTES_PER_POINT_TANGENT = BYTES_PER_POINT + 36 * 8            # 481
 # FETCH_SIZE / WRITE_SIZE (scaled by a 1 GiB copy calibration), keyed by the
 # hash of the kernel sources they were taken on; a changed kernel reports
 # traffic null until it is measured again.
-MEASURED_TRAFFIC = {"99fad3151dd2637f": 3.483e9}
+MEASURED_TRAFFIC = {"d3000db175cd137d": 3.484e9}
 # Executed FP64 FLOP per point of the forward kernel on the 256^3 batch
 # (rocprofv3 SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes / points), same keying.
-MEASURED_FP64_FLOP_PER_POINT = {"99fad3151dd2637f": 1428.0}
+MEASURED_FP64_FLOP_PER_POINT = {"d3000db175cd137d": 1433.0}
 KERNEL_SOURCES = ["automat.hip", "ad.hpp", "fastmath.hpp", "linalg6.hpp", "msgsm.hpp",
                   "gsm_point.hpp", "gsm_kernel.hpp"]
 
@@ -86,9 +86,10 @@ def time_calls(fn, steps, warmup, stream):
     return total_ms, each, wall
 
 
-def cpu_baseline(ps, budget_s=15.0):
+def cpu_baseline(ps, budget_s=30.0):
     """Time the oracle on growing prefixes of the batch until one takes at
-    least budget_s/3 seconds (or the whole batch is done)."""
+    least budget_s/3 seconds; if the whole batch is quicker than that, time
+    repeated passes over it until budget_s/3 seconds have accumulated."""
     import oracle
     n_total = ps.n
     m = 1 << 16
@@ -97,13 +98,19 @@ def cpu_baseline(ps, budget_s=15.0):
         eps = np.ascontiguousarray(ps.eps[:, :m])
         a_old = np.ascontiguousarray(ps.a_old[:, :m])
         phase = np.ascontiguousarray(ps.phase[:m])
-        t0 = time.perf_counter()
-        oracle.evaluate(eps, a_old, phase, ps.phases, h=ps.h, tol=ps.tol, max_iter=ps.max_iter)
-        dt = time.perf_counter() - t0
+        reps, dt = 0, 0.0
+        while True:
+            t0 = time.perf_counter()
+            oracle.evaluate(eps, a_old, phase, ps.phases, h=ps.h, tol=ps.tol, max_iter=ps.max_iter)
+            dt += time.perf_counter() - t0
+            reps += 1
+            if m < n_total or dt >= budget_s / 3:
+                break
         if dt >= budget_s / 3 or m == n_total:
-            return dict(value=m / dt, unit="updates/s", cores=oracle.num_threads(), kind="oracle",
+            return dict(value=m * reps / dt, unit="updates/s", cores=oracle.num_threads(),
+                        kind="oracle",
                         sample=f"first {m} of {n_total} points of the 256^3 fibre batch, "
-                               f"no tangent, {dt:.2f} s")
+                               f"no tangent, {reps} pass(es), {dt:.2f} s")
         m *= 4
 
 
@@ -167,22 +174,24 @@ def ms_tc_bench(steps, N=150, tol=1e-6):
         ms.set_macro([0.0] * 6)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        iters, curve = [], []
+        iters, curve, fails = [], [], 0
         for e in path:
             mean, Er, it, _ = ms.step_mixed(phase, [e, 0, 0, 0, 0, 0], h, eps, a, 0b111110)
             iters.append(it)
             curve.append((e, mean[0]))
+            fails += ms.newton_failures()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         ms.close()
         total = sum(iters)
         key = "reference_update" if upd else "reference_fixed"
         out[key] = {"wall_s": wall, "iterations_total": total, "iterations": iters,
+                    "point_solves_not_converged": fails,
                     "ms_per_iteration": wall / total * 1e3,
                     "sweep_updates_per_s": total * n / wall,
                     "stress_strain": curve[:: max(1, steps // 16)] + [curve[-1]]}
         log(f"[bench] MS tension-compression {N}^3 ({key}): {steps} steps, {total} iterations, "
-            f"{wall:.2f} s, {wall / total * 1e3:.3f} ms/iteration")
+            f"{wall:.2f} s, {wall / total * 1e3:.3f} ms/iteration, {fails} point solves not converged")
         del eps, a
     return out
 
@@ -286,7 +295,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": MEASURED_TRAFFIC.get(kernel_source_hash()),
-            "kernel": "gsm_eval_kernel<false>",
+            "kernel": "gsm_eval_kernel<false, false>",
             "kernel_source_hash": kernel_source_hash(),
             "bytes_per_point": BYTES_PER_POINT,
         },

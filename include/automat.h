@@ -100,8 +100,11 @@ typedef struct automat_params {
  *  params      host   phase table                                     (in)
  *  h           step length t_{n+1} - t_n, finite and > 0
  *  tol         Newton tolerance (> 0): converged when
- *              ||F||_inf <= tol ||a_{n+1} - a_n||_inf after >= 1 update,
- *              or when F vanishes exactly (no flow)
+ *              ||F||_inf <= max(tol ||a_{n+1} - a_n||_inf,
+ *                               2^-48 ||eps_new - a_old||_inf)
+ *              (F the implicit-Euler residual; the second term is the
+ *              rounding level of the trial elastic strain, reached by flows
+ *              just above the yield stress), or when F vanishes exactly
  *  max_iter    maximum number of Newton updates (>= 1)
  *  sigma_out   [6][n] stress sigma_{n+1}                              (out)
  *  a_out       [6][n] a_{n+1}, may equal a_old; NULL skips the write  (out)
@@ -195,6 +198,14 @@ typedef struct automat_ms_options {
                                 the reference then stays in use until the next update
                                 (automat_ms_reference reports it). 0: fixed. Needs
                                 36 more doubles per voxel (allocated on the first step) */
+    int32_t warm_start;      /* 1: each sweep's per-point Newton solves start from the
+                                increments of the previous sweep (the last step's for a
+                                step's first sweep; a start without flow is replaced by
+                                the elastic trial state), which saves Newton updates for
+                                strongly nonlinear laws at 96 bytes per voxel and sweep
+                                of extra traffic; 0: every solve starts from the elastic
+                                trial state */
+    int32_t reserved;        /* must be 0 */
 } automat_ms_options;
 
 /* Create a solver for an nx * ny * nz grid (each >= 2). params and opts are
@@ -242,6 +253,11 @@ int32_t automat_ms_step_mixed(automat_ms *ms, const uint8_t *phase, const double
 /* Set the macroscopic strain the next step starts from (e.g. after loading
  * a checkpointed strain field). */
 int32_t automat_ms_set_macro(automat_ms *ms, const double *E_previous);
+
+/* Point solves of the last completed load step (all its sweeps, the
+ * reference and commit sweeps included) that did not converge within
+ * newton_max_iter updates; their results are the last iterates. */
+int32_t automat_ms_newton_failures(const automat_ms *ms, uint64_t *count);
 
 /* The reference medium in use. */
 int32_t automat_ms_reference(const automat_ms *ms, double *lambda0, double *mu0);

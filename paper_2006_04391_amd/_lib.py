@@ -36,7 +36,8 @@ class MsOptions(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("fixed_iter", ctypes.c_int32), ("lambda0", ctypes.c_double),
                 ("mu0", ctypes.c_double), ("newton_tol", ctypes.c_double),
-                ("newton_max_iter", ctypes.c_int32), ("ref_update", ctypes.c_int32)]
+                ("newton_max_iter", ctypes.c_int32), ("ref_update", ctypes.c_int32),
+                ("warm_start", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -83,6 +84,7 @@ SIGNATURES = {
                                          _vp, _vp]),
     "automat_ms_create": (_i32, [_i32, _i32, _i32, _vp, _vp, _vp]),
     "automat_ms_step": (_i32, [_vp, _vp, _vp, _dbl, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "automat_ms_newton_failures": (_i32, [_vp, _vp]),
     "automat_ms_step_mixed": (_i32, [_vp, _vp, _vp, _vp, ctypes.c_uint32, _dbl, _vp, _vp, _vp,
                                       _vp, _vp, _vp, _vp, _vp]),
     "automat_ms_set_macro": (_i32, [_vp, _vp]),

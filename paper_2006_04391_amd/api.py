@@ -173,7 +173,8 @@ class MS:
     automat_ms_* entry points). shape = (nz, ny, nx), x fastest."""
 
     def __init__(self, shape, phases, *, tol=1e-6, max_iter=1000, fixed_iter=False, lambda0=0.0,
-                 mu0=0.0, newton_tol=1e-12, newton_max_iter=50, ref_update=False, device=None):
+                 mu0=0.0, newton_tol=1e-12, newton_max_iter=50, ref_update=False, warm_start=True,
+                 device=None):
         if isinstance(shape, int):
             shape = (shape, shape, shape)
         self.shape = tuple(int(s) for s in shape)
@@ -191,6 +192,7 @@ class MS:
         opts.newton_tol = float(newton_tol)
         opts.newton_max_iter = int(newton_max_iter)
         opts.ref_update = 1 if ref_update else 0
+        opts.warm_start = 1 if warm_start else 0
         self._opts = opts
         self._h = ctypes.c_void_p()
         lib = load()
@@ -205,6 +207,13 @@ class MS:
         check("automat_ms_reference", load().automat_ms_reference(self._h, ctypes.byref(lam),
                                                                    ctypes.byref(mu)))
         return lam.value, mu.value
+
+    def newton_failures(self):
+        """Point solves of the last load step that did not converge."""
+        c = ctypes.c_uint64()
+        check("automat_ms_newton_failures", load().automat_ms_newton_failures(self._h,
+                                                                             ctypes.byref(c)))
+        return c.value
 
     def set_macro(self, E_prev):
         E = (ctypes.c_double * 6)(*[float(x) for x in E_prev])

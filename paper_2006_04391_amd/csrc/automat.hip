@@ -42,6 +42,8 @@ struct EvalArgs {
     int32_t n_phases;
     int32_t polarize;  // nonzero: sigma_out receives sigma - C0 eps (basic scheme)
     double lam0, mu0;  // isotropic reference medium C0 for polarize
+    const double *guess;  // [6][n] initial increments of the Newton solves, or null (zero)
+    double *delta_out;    // [6][n] receives a_{n+1} - a_n, or null; may equal guess
     Model::Phase phases[AUTOMAT_MAX_PHASES];
 };
 
@@ -86,8 +88,10 @@ __device__ __forceinline__ void store_tangent(const EvalArgs &args, int64_t i, c
 }
 
 // Solve the queued points head .. head + cnt - 1 (cnt <= 64), lane l taking
-// ring slot head + l, and store their results.
-template <bool TANGENT>
+// ring slot head + l, and store their results. WARM: the Newton solves start
+// from args.guess and the increments go to args.delta_out (a separate
+// instantiation, so the plain kernels keep their register budget).
+template <bool TANGENT, bool WARM>
 __device__ __forceinline__ void run_batch(const EvalArgs &args, const PC *tab, double *ring,
                                           const int64_t *ridx, const int32_t *rpid, uint32_t head,
                                           uint32_t cnt, int lane) {
@@ -97,12 +101,24 @@ __device__ __forceinline__ void run_batch(const EvalArgs &args, const PC *tab, d
     const bool valid = active && raw < args.n_phases;  // invalid inputs carry an id past the table
     const int pid = valid ? raw : 0;
     const int64_t i = active ? ridx[slot] : 0;
-    double sig[6], anew[6], C[TANGENT ? 21 : 1];
-    const int status = solve_point<Model, TANGENT, kRing>(tab[pid], valid, ring + slot,
-                                                          ring + 6 * kRing + slot, args.h, args.tol,
-                                                          args.max_iter, args.flags, sig, anew, C);
+    const int64_t n = args.n;
+    double sig[6], anew[6], C[TANGENT ? 21 : 1], D[6] = {0, 0, 0, 0, 0, 0};
+    if (WARM && args.guess && valid) {
+        bool ok = true;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            D[c] = args.guess[c * n + i];
+            ok = ok && isfinite(D[c]);
+        }
+        if (!ok) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) D[c] = 0.0;
+        }
+    }
+    const int status = solve_point<Model, TANGENT, kRing, WARM>(
+        tab[pid], valid, ring + slot, ring + 6 * kRing + slot, args.h, args.tol, args.max_iter,
+        args.flags, D, sig, anew, C);
     if (active) {
-        const int64_t n = args.n;
         if (args.polarize) {
             double e[6];
 #pragma unroll
@@ -115,6 +131,10 @@ __device__ __forceinline__ void run_batch(const EvalArgs &args, const PC *tab, d
 #pragma unroll
             for (int c = 0; c < 6; ++c) __builtin_nontemporal_store(anew[c], args.a_out + c * n + i);
         }
+        if (WARM && args.delta_out) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) args.delta_out[c * n + i] = D[c];
+        }
         if constexpr (TANGENT) store_tangent<TANGENT>(args, i, C);
         if (args.iters) args.iters[i] = status;
     }
@@ -122,7 +142,7 @@ __device__ __forceinline__ void run_batch(const EvalArgs &args, const PC *tab, d
     wave_lds_sync();  // the slots may be refilled next
 }
 
-template <bool TANGENT>
+template <bool TANGENT, bool WARM>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(AUTOMAT_EVAL_WAVES)))
 void gsm_eval_kernel(const EvalArgs args) {
     extern __shared__ double smem_raw[];
@@ -228,6 +248,10 @@ void gsm_eval_kernel(const EvalArgs args) {
                     for (int c = 0; c < 6; ++c)
                         __builtin_nontemporal_store(a[c], args.a_out + c * n + i);
                 }
+                if (WARM && args.delta_out) {
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) args.delta_out[c * n + i] = 0.0;
+                }
                 if constexpr (TANGENT) {
                     double C[21];
 #pragma unroll
@@ -257,7 +281,7 @@ void gsm_eval_kernel(const EvalArgs args) {
         const uint32_t cnt = tail - head;
         if (cnt >= 64 || (!more && cnt > 0)) {
             const uint32_t take = cnt < 64 ? cnt : 64;
-            run_batch<TANGENT>(args, tab, ring, ridx, rpid, head, take, lane);
+            run_batch<TANGENT, WARM>(args, tab, ring, ridx, rpid, head, take, lane);
             head += take;
         }
         if (!more && tail == head) break;
@@ -286,10 +310,10 @@ static int32_t device_info(DeviceInfo &out) {
         if (hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             return AUTOMAT_EHIP;
         const size_t smem = eval_smem_bytes(AUTOMAT_MAX_PHASES);
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&d.blocks_fwd, gsm_eval_kernel<false>,
-                                                         kBlock, smem) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&d.blocks_tan, gsm_eval_kernel<true>,
-                                                         kBlock, smem) != hipSuccess)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &d.blocks_fwd, gsm_eval_kernel<false, false>, kBlock, smem) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &d.blocks_tan, gsm_eval_kernel<true, false>, kBlock, smem) != hipSuccess)
             return AUTOMAT_EHIP;
         if (d.blocks_fwd < 1) d.blocks_fwd = 1;
         if (d.blocks_tan < 1) d.blocks_tan = 1;
@@ -353,7 +377,8 @@ static int32_t launch_evaluate(int64_t n, const double *eps_new, const double *a
                                const uint8_t *phase, const automat_params *params, double h,
                                double tol, int32_t max_iter, double *sigma_out, double *a_out,
                                double *tangent_out, int32_t *iters_out, uint64_t *nonconverged,
-                               uint32_t flags, const double *pol, void *stream);
+                               uint32_t flags, const double *pol, const double *guess,
+                               double *delta_out, void *stream);
 
 extern "C" int32_t automat_evaluate_ex(int64_t n, const double *eps_new, const double *a_old,
                                        const uint8_t *phase, const automat_params *params,
@@ -361,17 +386,27 @@ extern "C" int32_t automat_evaluate_ex(int64_t n, const double *eps_new, const d
                                        double *a_out, double *tangent_out, int32_t *iters_out,
                                        uint64_t *nonconverged, uint32_t flags, void *stream) {
     return launch_evaluate(n, eps_new, a_old, phase, params, h, tol, max_iter, sigma_out, a_out,
-                           tangent_out, iters_out, nonconverged, flags, nullptr, stream);
+                           tangent_out, iters_out, nonconverged, flags, nullptr, nullptr, nullptr,
+                           stream);
 }
 
 namespace automat {
 int32_t evaluate_polarized(int64_t n, const double *eps, const double *a_old,
                            const uint8_t *phase, const automat_params *params, double h,
                            double tol, int32_t max_iter, double lam0, double mu0, double *tau_out,
-                           void *stream) {
+                           double *delta, uint64_t *nonconverged, void *stream) {
     const double pol[2] = {lam0, mu0};
     return launch_evaluate(n, eps, a_old, phase, params, h, tol, max_iter, tau_out, nullptr,
-                           nullptr, nullptr, nullptr, 0u, pol, stream);
+                           nullptr, nullptr, nonconverged, 0u, pol, delta, delta, stream);
+}
+
+int32_t evaluate_warm(int64_t n, const double *eps, const double *a_old, const uint8_t *phase,
+                      const automat_params *params, double h, double tol, int32_t max_iter,
+                      double *sigma_out, double *a_out, double *tangent_out, const double *guess,
+                      double *delta_out, uint64_t *nonconverged, void *stream) {
+    return launch_evaluate(n, eps, a_old, phase, params, h, tol, max_iter, sigma_out, a_out,
+                           tangent_out, nullptr, nonconverged, 0u, nullptr, guess, delta_out,
+                           stream);
 }
 }  // namespace automat
 
@@ -379,7 +414,8 @@ static int32_t launch_evaluate(int64_t n, const double *eps_new, const double *a
                                const uint8_t *phase, const automat_params *params, double h,
                                double tol, int32_t max_iter, double *sigma_out, double *a_out,
                                double *tangent_out, int32_t *iters_out, uint64_t *nonconverged,
-                               uint32_t flags, const double *pol, void *stream) {
+                               uint32_t flags, const double *pol, const double *guess,
+                               double *delta_out, void *stream) {
     if (n < 0) return AUTOMAT_EINVAL;
     if (!std::isfinite(h) || !(h > 0.0) || !std::isfinite(tol) || !(tol > 0.0) || max_iter < 1)
         return AUTOMAT_EINVAL;
@@ -408,6 +444,8 @@ static int32_t launch_evaluate(int64_t n, const double *eps_new, const double *a
         args.lam0 = pol[0];
         args.mu0 = pol[1];
     }
+    args.guess = guess;
+    args.delta_out = delta_out;
 
     DeviceInfo dev;
     rc = device_info(dev);
@@ -420,10 +458,16 @@ static int32_t launch_evaluate(int64_t n, const double *eps_new, const double *a
     const int grid = (int)(tiles < cap ? tiles : cap);
     const size_t smem = eval_smem_bytes(args.n_phases);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    if (tangent_out)
-        hipLaunchKernelGGL(gsm_eval_kernel<true>, dim3(grid), dim3(kBlock), smem, s, args);
+    const bool warm = guess || delta_out;
+    if (tangent_out && warm)
+        hipLaunchKernelGGL((gsm_eval_kernel<true, true>), dim3(grid), dim3(kBlock), smem, s, args);
+    else if (tangent_out)
+        hipLaunchKernelGGL((gsm_eval_kernel<true, false>), dim3(grid), dim3(kBlock), smem, s, args);
+    else if (warm)
+        hipLaunchKernelGGL((gsm_eval_kernel<false, true>), dim3(grid), dim3(kBlock), smem, s, args);
     else
-        hipLaunchKernelGGL(gsm_eval_kernel<false>, dim3(grid), dim3(kBlock), smem, s, args);
+        hipLaunchKernelGGL((gsm_eval_kernel<false, false>), dim3(grid), dim3(kBlock), smem, s,
+                           args);
     if (hipGetLastError() != hipSuccess) return AUTOMAT_EHIP;
     return AUTOMAT_OK;
 }

@@ -9,6 +9,9 @@
 namespace automat {
 
 constexpr int kBlock = 256;
+// Newton updates after which a warm-started solve restarts from the elastic
+// trial state (see solve_point)
+constexpr int kWarmRestart = 6;
 
 // Keeps the compiler from hoisting LDS reads (per-phase constants, the
 // staged inputs) out of the Newton loop into registers: they are cheap to
@@ -48,29 +51,66 @@ __device__ __forceinline__ void count_failures(unsigned long long *counter, bool
 
 // Solve one point (all lanes of the wave call this; the Newton loop exits
 // when a ballot shows every lane done). eps, an: this lane's LDS staging
-// (component c at [c * S]). Returns the number of Newton updates, or
-// -1 (not converged within max_iter, or invalid input). Outputs sigma,
-// a_{n+1} and, if TANGENT, the packed consistent tangent C[21].
-template <class Model, bool TANGENT, int S = kBlock>
+// (component c at [c * S]). D: on entry the initial increment (zero, or a
+// warm start such as the solution at a nearby strain), on return the
+// increment a_{n+1} - a_n (zero without flow). Returns the number of Newton
+// updates, or -1 (not converged within max_iter, or invalid input). Outputs
+// sigma, a_{n+1} and, if TANGENT, the packed consistent tangent C[21].
+// WARM: D may be non-zero on entry (otherwise it must be zero).
+template <class Model, bool TANGENT, int S = kBlock, bool WARM = false>
 __device__ __forceinline__ int solve_point(const PhaseConst<Model> &pc, bool valid, const double *eps,
                                            const double *an, double h, double tol, int max_iter,
-                                           unsigned flags, double *sig, double *anew, double *C) {
+                                           unsigned flags, double *D, double *sig, double *anew,
+                                           double *C) {
     const typename Model::Phase &prm = pc.prm;
     const bool newton = valid && Model::flows(prm);
 
-    double D[6] = {0, 0, 0, 0, 0, 0};
+    if (!newton) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) D[c] = 0.0;
+    }
     Resid2 cur;
     // cur.M holds the Newton matrix of the current point only when have_M:
     // a trial predicted to end the iteration is evaluated to first order.
     bool have_M = true;
+    // merit value Phi(D) = D.K.D / 2 + h Psi(A(D)), the scale of the line
+    // search's round-off allowance
     double phi = 0.0;
     int status = valid ? 0 : -1;
     if (newton) {
         residual2<Model>(prm, pc.Kinv, Strided<S>{eps}, Strided<S>{an}, D, h, cur);
+        if constexpr (WARM) {
+            // A guess without flow (F = D exactly: f = Psi'' = 0 there) is
+            // replaced by D = 0, the elastic trial state. From the no-flow
+            // side the Newton model sees no curvature, and the line search
+            // would creep towards a solution across the yield surface one
+            // halving at a time; from the trial state the iteration comes
+            // from the flowing side, as without a warm start.
+            bool nf = false;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) nf = nf || (D[c] != 0.0);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) nf = nf && (cur.F[c] == D[c]);
+            if (nf) {
+#pragma unroll
+                for (int c = 0; c < 6; ++c) D[c] = 0.0;
+                residual2<Model>(prm, pc.Kinv, Strided<S>{eps}, Strided<S>{an}, D, h, cur);
+            }
+        }
         phi = h * cur.psi;
+        if constexpr (WARM) {
+            double kd[6];
+            la::symv6(pc.K, D, kd);
+            phi += 0.5 * la::dot6(D, kd);
+        }
     }
     bool done = !newton;
     int k = 0;
+    // rounding level of the trial elastic strain (convergence floor below)
+    double floor_F = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) floor_F = fmax(floor_F, fabs(eps[c * S] - an[c * S]));
+    floor_F *= 0x1p-48;
     for (;;) {
         lds_reload_point();
         if (!done) {
@@ -78,12 +118,17 @@ __device__ __forceinline__ int solve_point(const PhaseConst<Model> &pc, bool val
 #pragma unroll
             for (int c = 0; c < 6; ++c) zero = zero && (cur.F[c] == 0.0);
             bool conv = zero;
-            if (!conv && k >= 1) {
-                if (flags & AUTOMAT_SIGMA_CRITERION)
-                    conv = sigma_converged<Model>(prm, Strided<S>{eps}, Strided<S>{an},
-                                                  D, cur.F, tol);
-                else
-                    conv = la::norm_inf6(cur.F) <= tol * la::norm_inf6(D);
+            if (!conv) {
+                if (flags & AUTOMAT_SIGMA_CRITERION) {
+                    conv = k >= 1 && sigma_converged<Model>(prm, Strided<S>{eps}, Strided<S>{an},
+                                                            D, cur.F, tol);
+                } else {
+                    // relative to the increment, or at the rounding level of
+                    // the trial elastic strain that F is computed from (a flow
+                    // just above the yield stress has an increment too small
+                    // for the relative test to be met)
+                    conv = la::norm_inf6(cur.F) <= fmax(tol * la::norm_inf6(D), floor_F);
+                }
             }
             if (conv) {
                 done = true;
@@ -114,6 +159,24 @@ __device__ __forceinline__ int solve_point(const PhaseConst<Model> &pc, bool val
                 status = -1;
             } else {
                 la::symv6(pc.Kinv, y, delta);
+                if constexpr (WARM) {
+                    // F = D exactly: no flow at D (f = Psi'' = 0 there), and
+                    // the Newton step lands on D = 0 exactly; taken without
+                    // its rounding, the next residual can be exactly zero.
+                    // A warm start still unconverged after kWarmRestart
+                    // updates also goes back to D = 0 (accepted without line
+                    // search, below): from some starting points the line
+                    // search creeps towards a solution across the yield
+                    // surface, while from the elastic trial state the
+                    // iteration converges as it does without a warm start.
+                    bool no_flow = true;
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) no_flow = no_flow && (cur.F[c] == D[c]);
+                    if (no_flow || k == kWarmRestart) {
+#pragma unroll
+                        for (int c = 0; c < 6; ++c) delta[c] = D[c];
+                    }
+                }
                 // quadratic convergence: a step this small relative to the
                 // new iterate leaves a residual far below tol
                 double dn = 0.0, nn = 0.0;
@@ -128,7 +191,9 @@ __device__ __forceinline__ int solve_point(const PhaseConst<Model> &pc, bool val
         // one kind of trial evaluation for the whole wave
         first_order = __ballot(!done && !first_order) == 0;
         if (!done) {
-            const double slope = la::dot6(cur.F, y);
+            double slope = la::dot6(cur.F, y);
+            if constexpr (WARM)
+                if (k == kWarmRestart) slope = -INFINITY;  // accept the restart
             const double s1 = la::dot6(D, y), s2 = la::dot6(delta, y);
             const double psi0 = cur.psi;
             // full step first; a rejected trial D - t delta moves to
@@ -151,6 +216,8 @@ __device__ __forceinline__ int solve_point(const PhaseConst<Model> &pc, bool val
             }
             have_M = !first_order;
             phi += dphi;
+            if constexpr (WARM)
+                if (k == kWarmRestart) phi = h * cur.psi;  // Phi(0)
             ++k;
         }
     }

@@ -50,6 +50,7 @@ template <class Model>
 struct PhaseConst {
     typename Model::Phase prm;
     double Kinv[21];   // (d2 omega / da2)^-1, packed
+    double K[21];      // d2 omega / da2, packed (merit value at a warm start)
     double Cee[21];    // d2 omega / deps2, packed (elastic stiffness)
     double C0[21];     // Cee - Kea Kinv Kae, packed
     double R[36];      // Kinv Kae, row-major (row a, column eps)
@@ -66,6 +67,7 @@ AD_FN bool build_phase_const(const typename Model::Phase &p, PhaseConst<Model> &
 #pragma unroll
     for (int i = 0; i < 21; ++i) {
         L[i] = Kaa[i];
+        pc.K[i] = Kaa[i];
         pc.Cee[i] = Kee[i];
     }
     const bool ok = la::cholesky6(L, idg);

@@ -386,9 +386,14 @@ struct automat_ms {
     double E_prev[6];
     hipfftHandle fwd, inv;
     double *sig;   // [6][n] stress / polarization / raw inverse FFT output
+    double *dlt;   // [6][n] increments a_{n+1} - a_n of the last sweep: the next
+                   // sweep's Newton solves start there (warm start)
     hipfftDoubleComplex *spec;  // [6][nh]
     double *partial;            // [6 * kRedBlocks]
     double *scal;               // [16] reduced scalars; [8..13] the macro strain
+    uint64_t *fails;            // device: point solves of the current step that failed
+    uint64_t *host_fails;       // pinned
+    uint64_t last_fails;        // of the last completed step
     double *host_scal;          // pinned [16]
     // reverse step work space, allocated on first use
     double *tan;                // [36][n] consistent tangent at the converged strain
@@ -401,6 +406,8 @@ static int32_t ms_check_opts(const automat_ms_options *o) {
     if (!o) return AUTOMAT_EINVAL;
     if (o->max_iter < 1 || o->newton_max_iter < 1) return AUTOMAT_EINVAL;
     if (o->ref_update != 0 && o->ref_update != 1) return AUTOMAT_EINVAL;
+    if (o->warm_start != 0 && o->warm_start != 1) return AUTOMAT_EINVAL;
+    if (o->reserved != 0) return AUTOMAT_EINVAL;
     if (!o->fixed_iter && !(o->tol > 0.0)) return AUTOMAT_EINVAL;
     if (!(o->newton_tol > 0.0)) return AUTOMAT_EINVAL;
     return AUTOMAT_OK;
@@ -448,10 +455,14 @@ extern "C" int32_t automat_ms_create(int32_t nx, int32_t ny, int32_t nz,
     const size_t nb = (size_t)m->f.n * 6 * sizeof(double);
     const size_t nc = (size_t)m->f.nh * 6 * sizeof(hipfftDoubleComplex);
     bool ok = hipMalloc(&m->sig, nb) == hipSuccess &&
+              (!opts->warm_start ||
+               (hipMalloc(&m->dlt, nb) == hipSuccess && hipMemset(m->dlt, 0, nb) == hipSuccess)) &&
               hipMalloc(&m->spec, nc) == hipSuccess &&
               hipMalloc(&m->partial, 6 * kRedBlocks * sizeof(double)) == hipSuccess &&
               hipMalloc(&m->scal, 16 * sizeof(double)) == hipSuccess &&
-              hipHostMalloc(&m->host_scal, 16 * sizeof(double), hipHostMallocDefault) == hipSuccess;
+              hipHostMalloc(&m->host_scal, 16 * sizeof(double), hipHostMallocDefault) == hipSuccess &&
+              hipMalloc(&m->fails, sizeof(uint64_t)) == hipSuccess &&
+              hipHostMalloc(&m->host_fails, sizeof(uint64_t), hipHostMallocDefault) == hipSuccess;
     ok = ok && hipfftPlanMany(&m->fwd, 3, dims, dims, 1, (int)m->f.n, dims_c, 1, (int)m->f.nh,
                               HIPFFT_D2Z, 6) == HIPFFT_SUCCESS;
     ok = ok && hipfftPlanMany(&m->inv, 3, dims, dims_c, 1, (int)m->f.nh, dims, 1, (int)m->f.n,
@@ -469,10 +480,13 @@ extern "C" int32_t automat_ms_destroy(automat_ms *m) {
     if (m->fwd) (void)hipfftDestroy(m->fwd);
     if (m->inv) (void)hipfftDestroy(m->inv);
     if (m->sig) (void)hipFree(m->sig);
+    if (m->dlt) (void)hipFree(m->dlt);
     if (m->spec) (void)hipFree(m->spec);
     if (m->partial) (void)hipFree(m->partial);
     if (m->scal) (void)hipFree(m->scal);
     if (m->host_scal) (void)hipHostFree(m->host_scal);
+    if (m->fails) (void)hipFree(m->fails);
+    if (m->host_fails) (void)hipHostFree(m->host_fails);
     if (m->tan) (void)hipFree(m->tan);
     if (m->lam) (void)hipFree(m->lam);
     if (m->rhs) (void)hipFree(m->rhs);
@@ -492,6 +506,9 @@ static double tensor_norm(const double *e) {
     return sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2] +
                 0.5 * (e[3] * e[3] + e[4] * e[4] + e[5] * e[5]));
 }
+
+// the warm-start buffer, or null without warm starts
+static double *warm(automat_ms *m) { return m->opts.warm_start ? m->dlt : nullptr; }
 
 static int32_t ensure_buffer(double **p, size_t bytes) {
     if (*p) return AUTOMAT_OK;
@@ -518,9 +535,9 @@ static int32_t update_reference(automat_ms *m, const uint8_t *phase, double h, c
     const int64_t n = m->f.n;
     int32_t rc = ensure_buffer(&m->tan, (size_t)n * 36 * sizeof(double));
     if (rc) return rc;
-    rc = automat_evaluate_ex(n, eps, a, phase, &m->params, h, m->opts.newton_tol,
-                             m->opts.newton_max_iter, m->sig, nullptr, m->tan, nullptr, nullptr,
-                             0u, s);
+    rc = evaluate_warm(n, eps, a, phase, &m->params, h, m->opts.newton_tol,
+                       m->opts.newton_max_iter, m->sig, nullptr, m->tan, warm(m), nullptr,
+                       m->fails, s);
     if (rc) return rc;
     hipLaunchKernelGGL(iso_minmax_kernel, dim3(rb), dim3(kRedBlock), 0, s, m->tan, n, m->partial);
     hipLaunchKernelGGL(finish_minmax_kernel, dim3(4), dim3(kRedBlock), 0, s, m->partial, rb,
@@ -550,6 +567,7 @@ extern "C" int32_t automat_ms_step_mixed(automat_ms *m, const uint8_t *phase,
     const int gb = (int)((n + tb - 1) / tb);
     if (hipfftSetStream(m->fwd, s) != HIPFFT_SUCCESS || hipfftSetStream(m->inv, s) != HIPFFT_SUCCESS)
         return AUTOMAT_EHIP;
+    if (hipMemsetAsync(m->fails, 0, sizeof(uint64_t), s) != hipSuccess) return AUTOMAT_EHIP;
     MacroBC bc;
     for (int c = 0; c < 6; ++c) {
         bc.E[c] = (stress_mask >> c & 1u) ? 0.0 : E_macro[c];
@@ -586,7 +604,8 @@ extern "C" int32_t automat_ms_step_mixed(automat_ms *m, const uint8_t *phase,
     for (it = 1; it <= m->opts.max_iter; ++it) {
         // material sweep writing the polarization tau = sigma - C0 eps
         rc = evaluate_polarized(n, eps, a, phase, &m->params, h, m->opts.newton_tol,
-                                m->opts.newton_max_iter, m->lam0, m->mu0, m->sig, stream);
+                                m->opts.newton_max_iter, m->lam0, m->mu0, m->sig, warm(m),
+                                m->fails, stream);
         if (rc) return rc;
         if (hipfftExecD2Z(m->fwd, m->sig, m->spec) != HIPFFT_SUCCESS) return AUTOMAT_EHIP;
         hipLaunchKernelGGL(gamma_kernel, dim3(nhb), dim3(tb), 0, s, m->spec, m->f, m->lam0,
@@ -606,9 +625,9 @@ extern "C" int32_t automat_ms_step_mixed(automat_ms *m, const uint8_t *phase,
     if (it > m->opts.max_iter) it = m->opts.max_iter;
     // commit: sweep at the converged strain, a_n <- a_{n+1}
     double *sig = sigma_out ? sigma_out : m->sig;
-    rc = automat_evaluate_ex(n, eps, a, phase, &m->params, h, m->opts.newton_tol,
-                             m->opts.newton_max_iter, sig, a, nullptr, nullptr, nullptr, 0u,
-                             stream);
+    rc = evaluate_warm(n, eps, a, phase, &m->params, h, m->opts.newton_tol,
+                       m->opts.newton_max_iter, sig, a, nullptr, warm(m), warm(m), m->fails,
+                       stream);
     if (rc) return rc;
     if (sigma_mean) {
         hipLaunchKernelGGL(mean6_kernel, dim3(rb), dim3(kRedBlock), 0, s, sig, n, m->partial);
@@ -617,6 +636,11 @@ extern "C" int32_t automat_ms_step_mixed(automat_ms *m, const uint8_t *phase,
         if (rc) return rc;
         for (int c = 0; c < 6; ++c) sigma_mean[c] = m->host_scal[c] / (double)n;
     }
+    if (hipMemcpyAsync(m->host_fails, m->fails, sizeof(uint64_t), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return AUTOMAT_EHIP;
+    m->last_fails = *m->host_fails;
     for (int c = 0; c < 6; ++c) {
         m->E_prev[c] = Ecur[c];
         if (E_reached) E_reached[c] = Ecur[c];
@@ -633,6 +657,12 @@ extern "C" int32_t automat_ms_step(automat_ms *m, const uint8_t *phase, const do
                                    void *stream) {
     return automat_ms_step_mixed(m, phase, E_macro, nullptr, 0u, h, eps, a, sigma_out, sigma_mean,
                                  nullptr, iters, residual, stream);
+}
+
+extern "C" int32_t automat_ms_newton_failures(const automat_ms *m, uint64_t *count) {
+    if (!m || !count) return AUTOMAT_EINVAL;
+    *count = m->last_fails;
+    return AUTOMAT_OK;
 }
 
 extern "C" int32_t automat_ms_set_macro(automat_ms *m, const double *E_prev) {

@@ -134,10 +134,10 @@ __device__ __forceinline__ void serve_run_batch(const Segment &sg, const PC *tab
     const bool active = (uint32_t)lane < cnt;
     const int pid = active ? rpid[slot] : 0;
     const int64_t i = active ? ridx[slot] : 0;
-    double sig[6], anew[6];
+    double sig[6], anew[6], D[6] = {0, 0, 0, 0, 0, 0};
     const int status = solve_point<Model, false, kRing>(tab[pid], active, ring + slot,
                                                         ring + 6 * kRing + slot, sg.h, sg.tol,
-                                                        sg.max_iter, 0u, sig, anew, nullptr);
+                                                        sg.max_iter, 0u, D, sig, anew, nullptr);
     if (active) {
         const int64_t n = sg.n;
 #pragma unroll

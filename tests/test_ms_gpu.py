@@ -25,7 +25,7 @@ def _gpu_run(shape, phase, phases, loads, h, **opts):
         mean, it, res = ms.step(ph, E, h, eps, a, sigma_out=sig)
         torch.cuda.synchronize()
         out.append(dict(eps=N(eps), a=N(a), sigma=N(sig), sigma_mean=np.array(mean), iters=it,
-                        residual=res))
+                        residual=res, failures=ms.newton_failures()))
     ms.close()
     return out
 
@@ -82,6 +82,7 @@ def test_lockstep_parity_viscoplastic(shape):
     o = _oracle_run(shape, phase, ph, loads, 1.0, tol=0.0, **kw)
     for gs, os_ in zip(g, o):
         assert gs["iters"] == os_["iters"] == 12
+        assert gs["failures"] == 0
         for key in ("eps", "a", "sigma"):
             assert _rel(gs[key], os_[key]) <= 1e-10, key
         np.testing.assert_allclose(gs["sigma_mean"], os_["sigma_mean"], rtol=1e-10,
@@ -132,7 +133,8 @@ def _gpu_run_mixed(shape, phase, phases, loads, h, mask, S=None, **opts):
         torch.cuda.synchronize()
         lam0, mu0 = ms.reference()
         out.append(dict(eps=N(eps), a=N(a), sigma=N(sig), sigma_mean=np.array(mean),
-                        E=np.array(Er), iters=it, residual=res, lam0=lam0, mu0=mu0))
+                        E=np.array(Er), iters=it, residual=res, lam0=lam0, mu0=mu0,
+                        failures=ms.newton_failures()))
     ms.close()
     return out
 
@@ -197,6 +199,7 @@ def test_lockstep_parity_mixed(shape, upd):
     o = _oracle_run_mixed(shape, phase, ph, loads, 1.0, UNIAXIAL, tol=0.0, **kw)
     for gs, os_ in zip(g, o):
         assert gs["iters"] == os_["iters"] == 12
+        assert gs["failures"] == 0
         for key in ("eps", "a", "sigma"):
             assert _rel(gs[key], os_[key]) <= 1e-10, key
         np.testing.assert_allclose(gs["E"], os_["E"], rtol=1e-10, atol=1e-10 * abs(os_["E"][0]))
