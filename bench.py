@@ -122,7 +122,9 @@ def ms_bench(steps, N=128, h=0.1, tol=1e-6):
     from paper_2006_04391_amd import api, inputs
     phase = torch.from_numpy(inputs.sphere_phase(N, seed=2)).cuda()
     n = N ** 3
-    ms = api.MS((N, N, N), inputs.config_phases(), tol=tol, max_iter=5000)
+    # cold Newton starts: with these mildly nonlinear parameters a warm start
+    # saves fewer updates than its extra traffic costs
+    ms = api.MS((N, N, N), inputs.config_phases(), tol=tol, max_iter=5000, warm_start=False)
     eps = torch.zeros((6, n), dtype=torch.float64, device="cuda")
     a = torch.zeros_like(eps)
     ms.step(phase, [0.0] * 6, h, eps, a)       # warm-up (plans, modules)
@@ -143,7 +145,8 @@ def ms_bench(steps, N=128, h=0.1, tol=1e-6):
     log(f"[bench] MS {N}^3: {steps} steps, {total} iterations, {wall:.2f} s, "
         f"{wall / total * 1e3:.3f} ms/iteration")
     return {"workload": f"Moulinec-Suquet basic scheme, {N}^3 periodic spheres (20 %, r=6), "
-                        f"uniaxial strain rate 1e-3/s, {steps} steps of h={h} s, tol {tol}",
+                        f"uniaxial strain rate 1e-3/s, {steps} steps of h={h} s, tol {tol}, "
+                        f"cold Newton starts",
             "wall_s": wall, "iterations": iters, "ms_per_iteration": wall / total * 1e3,
             "sweep_updates_per_s": total * n / wall, "sigma_mean_last": mean}
 
@@ -328,6 +331,32 @@ def main():
                            "ms_per_step": ms_cv, "value": n / (ms_cv * 1e-3), "unit": "updates/s",
                            "automatic_over_conventional_time": ms / ms_cv}
     log(f"[bench] conventional: {ms_cv:.3f} ms/step (automatic / conventional = {ms / ms_cv:.2f})")
+
+    # the paper's semi-automatic strategy: the same Newton solve and tangent
+    # with hand-derived partials of omega and Psi instead of AD
+    from paper_2006_04391_amd import _lib as _l
+
+    def step_sa():
+        api.evaluate(eps, a_old, phase, ps.phases, ps.h, ps.tol, ps.max_iter,
+                     sigma_out=sigma, a_out=a_new, flags=_l.HAND_PARTIALS)
+    ts, _, _ = time_calls(step_sa, max(3, args.steps // 2), 2, stream)
+    ms_sa = ts / max(3, args.steps // 2)
+    sa = {"workload": "same 256^3 batch, hand-derived partials in the generic Newton solve",
+          "ms_per_step": ms_sa, "value": n / (ms_sa * 1e-3), "unit": "updates/s",
+          "automatic_over_semi_automatic_time": ms / ms_sa}
+    if not args.no_tangent:
+        def step_sat():
+            api.evaluate(eps, a_old, phase, ps.phases, ps.h, ps.tol, ps.max_iter,
+                         sigma_out=sigma, a_out=a_new, tangent=True, flags=_l.HAND_PARTIALS)
+        tst, _, _ = time_calls(step_sat, max(3, args.steps // 4), 1, stream)
+        sa["tangent_ms_per_step"] = tst / max(3, args.steps // 4)
+        if "tangent" in out:
+            sa["automatic_over_semi_automatic_time_tangent"] = (out["tangent"]["ms_per_step"] /
+                                                                sa["tangent_ms_per_step"])
+    out["semi_automatic"] = sa
+    log(f"[bench] semi-automatic: {ms_sa:.3f} ms/step (automatic / semi-automatic = "
+        f"{ms / ms_sa:.2f})" + (f", tangent {sa['tangent_ms_per_step']:.3f} ms/step"
+                               if "tangent_ms_per_step" in sa else ""))
 
     if not args.no_rk23:
         # adaptive explicit Runge-Kutta over one load step of the same batch:

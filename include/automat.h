@@ -68,6 +68,10 @@ extern "C" {
 #define AUTOMAT_SIGMA_CRITERION 1u /* stop Newton on ||C F||_inf <= tol ||sigma||_inf,
                                       i.e. converge the stress (Section "Stress-Driven
                                       Error Control", last paragraph) */
+#define AUTOMAT_HAND_PARTIALS 2u   /* semi-automatic strategy: the same Newton solve and
+                                      tangent with hand-derived partials of omega and Psi
+                                      instead of automatic differentiation (Section
+                                      "Example", comparison of evaluation strategies) */
 
 /* One material phase (Section "Example", Table misu_parameters names the
  * same quantities).
@@ -126,7 +130,7 @@ int32_t automat_evaluate(int64_t n, const double *eps_new, const double *a_old,
  *               converged or invalid input; NULL skips it             (out)
  *  nonconverged device uint64 counter, incremented once per point with
  *               iters = -1 (not reset by the call); NULL skips it     (inout)
- *  flags        AUTOMAT_SIGMA_CRITERION or 0 */
+ *  flags        0, or AUTOMAT_SIGMA_CRITERION and/or AUTOMAT_HAND_PARTIALS */
 int32_t automat_evaluate_ex(int64_t n, const double *eps_new, const double *a_old,
                             const uint8_t *phase, const automat_params *params, double h,
                             double tol, int32_t max_iter, double *sigma_out, double *a_out,

@@ -18,6 +18,7 @@ GRAD_KEYS = ("E", "nu", "H", "sigma_y", "sigma0", "eps0", "n")
 
 OK, EINVAL, EHIP, ENOMEM, EBUDGET = 0, -1, -2, -3, -4
 SIGMA_CRITERION = 1
+HAND_PARTIALS = 2
 
 
 class Phase(ctypes.Structure):

@@ -20,6 +20,7 @@
 #include "automat.h"
 #include "gsm_kernel.hpp"
 #include "host_common.hpp"
+#include "msgsm_hand.hpp"
 
 namespace automat {
 
@@ -91,8 +92,8 @@ __device__ __forceinline__ void store_tangent(const EvalArgs &args, int64_t i, c
 // ring slot head + l, and store their results. WARM: the Newton solves start
 // from args.guess and the increments go to args.delta_out (a separate
 // instantiation, so the plain kernels keep their register budget).
-template <bool TANGENT, bool WARM>
-__device__ __forceinline__ void run_batch(const EvalArgs &args, const PC *tab, double *ring,
+template <class M, bool TANGENT, bool WARM>
+__device__ __forceinline__ void run_batch(const EvalArgs &args, const PhaseConst<M> *tab, double *ring,
                                           const int64_t *ridx, const int32_t *rpid, uint32_t head,
                                           uint32_t cnt, int lane) {
     const uint32_t slot = (head + (uint32_t)lane) & (kRing - 1);
@@ -115,7 +116,7 @@ __device__ __forceinline__ void run_batch(const EvalArgs &args, const PC *tab, d
             for (int c = 0; c < 6; ++c) D[c] = 0.0;
         }
     }
-    const int status = solve_point<Model, TANGENT, kRing, WARM>(
+    const int status = solve_point<M, TANGENT, kRing, WARM>(
         tab[pid], valid, ring + slot, ring + 6 * kRing + slot, args.h, args.tol, args.max_iter,
         args.flags, D, sig, anew, C);
     if (active) {
@@ -142,9 +143,12 @@ __device__ __forceinline__ void run_batch(const EvalArgs &args, const PC *tab, d
     wave_lds_sync();  // the slots may be refilled next
 }
 
-template <bool TANGENT, bool WARM>
+// M: MSGSM (partials of omega and Psi by automatic differentiation) or
+// MSGSMHand (hand-derived partials, the semi-automatic strategy).
+template <class M, bool TANGENT, bool WARM>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(AUTOMAT_EVAL_WAVES)))
 void gsm_eval_kernel(const EvalArgs args) {
+    using PC = PhaseConst<M>;
     extern __shared__ double smem_raw[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double *ring = smem_raw + wave * (kRingBytes / sizeof(double));
@@ -152,7 +156,7 @@ void gsm_eval_kernel(const EvalArgs args) {
     int32_t *rpid = reinterpret_cast<int32_t *>(ridx + kRing);
     PC *tab = reinterpret_cast<PC *>(smem_raw + kWaves * (kRingBytes / sizeof(double)));
     for (int k = threadIdx.x; k < args.n_phases; k += blockDim.x)
-        build_phase_const<Model>(args.phases[k], tab[k], TANGENT);
+        build_phase_const<M>(args.phases[k], tab[k], TANGENT);
     __syncthreads();
 
     const int64_t n = args.n;
@@ -229,12 +233,12 @@ void gsm_eval_kernel(const EvalArgs args) {
             const PC &pc = tab[valid ? pid : 0];
             // without compaction every point of the chunk goes through the
             // batch in lane order, which keeps the output stores coalesced
-            const bool queue = kCompact ? in_range && valid && Model::flows(pc.prm) : in_range;
+            const bool queue = kCompact ? in_range && valid && M::flows(pc.prm) : in_range;
             if (kCompact && in_range && !queue) {
                 // no flow: a_{n+1} = a_n, elastic stress and stiffness
                 double sig[6];
                 if (valid) {
-                    Model::stress(pc.prm, e, a, sig);
+                    M::stress(pc.prm, e, a, sig);
                     if (args.polarize) polarize6(sig, e, args.lam0, args.mu0);
                 } else {
 #pragma unroll
@@ -281,7 +285,7 @@ void gsm_eval_kernel(const EvalArgs args) {
         const uint32_t cnt = tail - head;
         if (cnt >= 64 || (!more && cnt > 0)) {
             const uint32_t take = cnt < 64 ? cnt : 64;
-            run_batch<TANGENT, WARM>(args, tab, ring, ridx, rpid, head, take, lane);
+            run_batch<M, TANGENT, WARM>(args, tab, ring, ridx, rpid, head, take, lane);
             head += take;
         }
         if (!more && tail == head) break;
@@ -311,9 +315,9 @@ static int32_t device_info(DeviceInfo &out) {
             return AUTOMAT_EHIP;
         const size_t smem = eval_smem_bytes(AUTOMAT_MAX_PHASES);
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &d.blocks_fwd, gsm_eval_kernel<false, false>, kBlock, smem) != hipSuccess ||
+                &d.blocks_fwd, gsm_eval_kernel<Model, false, false>, kBlock, smem) != hipSuccess ||
             hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &d.blocks_tan, gsm_eval_kernel<true, false>, kBlock, smem) != hipSuccess)
+                &d.blocks_tan, gsm_eval_kernel<Model, true, false>, kBlock, smem) != hipSuccess)
             return AUTOMAT_EHIP;
         if (d.blocks_fwd < 1) d.blocks_fwd = 1;
         if (d.blocks_tan < 1) d.blocks_tan = 1;
@@ -419,7 +423,9 @@ static int32_t launch_evaluate(int64_t n, const double *eps_new, const double *a
     if (n < 0) return AUTOMAT_EINVAL;
     if (!std::isfinite(h) || !(h > 0.0) || !std::isfinite(tol) || !(tol > 0.0) || max_iter < 1)
         return AUTOMAT_EINVAL;
-    if (flags & ~AUTOMAT_SIGMA_CRITERION) return AUTOMAT_EINVAL;
+    if (flags & ~(AUTOMAT_SIGMA_CRITERION | AUTOMAT_HAND_PARTIALS)) return AUTOMAT_EINVAL;
+    const bool hand = flags & AUTOMAT_HAND_PARTIALS;
+    if (hand && (guess || delta_out || pol)) return AUTOMAT_EINVAL;
     EvalArgs args;
     std::memset(&args, 0, sizeof args);
     int32_t rc = copy_params(params, args.phases, &args.n_phases);
@@ -459,15 +465,24 @@ static int32_t launch_evaluate(int64_t n, const double *eps_new, const double *a
     const size_t smem = eval_smem_bytes(args.n_phases);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const bool warm = guess || delta_out;
-    if (tangent_out && warm)
-        hipLaunchKernelGGL((gsm_eval_kernel<true, true>), dim3(grid), dim3(kBlock), smem, s, args);
-    else if (tangent_out)
-        hipLaunchKernelGGL((gsm_eval_kernel<true, false>), dim3(grid), dim3(kBlock), smem, s, args);
-    else if (warm)
-        hipLaunchKernelGGL((gsm_eval_kernel<false, true>), dim3(grid), dim3(kBlock), smem, s, args);
-    else
-        hipLaunchKernelGGL((gsm_eval_kernel<false, false>), dim3(grid), dim3(kBlock), smem, s,
+    if (hand && tangent_out)
+        hipLaunchKernelGGL((gsm_eval_kernel<MSGSMHand, true, false>), dim3(grid), dim3(kBlock),
+                           smem, s, args);
+    else if (hand)
+        hipLaunchKernelGGL((gsm_eval_kernel<MSGSMHand, false, false>), dim3(grid), dim3(kBlock),
+                           smem, s, args);
+    else if (tangent_out && warm)
+        hipLaunchKernelGGL((gsm_eval_kernel<Model, true, true>), dim3(grid), dim3(kBlock), smem, s,
                            args);
+    else if (tangent_out)
+        hipLaunchKernelGGL((gsm_eval_kernel<Model, true, false>), dim3(grid), dim3(kBlock), smem,
+                           s, args);
+    else if (warm)
+        hipLaunchKernelGGL((gsm_eval_kernel<Model, false, true>), dim3(grid), dim3(kBlock), smem,
+                           s, args);
+    else
+        hipLaunchKernelGGL((gsm_eval_kernel<Model, false, false>), dim3(grid), dim3(kBlock), smem,
+                           s, args);
     if (hipGetLastError() != hipSuccess) return AUTOMAT_EHIP;
     return AUTOMAT_OK;
 }
