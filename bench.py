@@ -354,9 +354,41 @@ def main():
             sa["automatic_over_semi_automatic_time_tangent"] = (out["tangent"]["ms_per_step"] /
                                                                 sa["tangent_ms_per_step"])
     out["semi_automatic"] = sa
+
     log(f"[bench] semi-automatic: {ms_sa:.3f} ms/step (automatic / semi-automatic = "
         f"{ms / ms_sa:.2f})" + (f", tangent {sa['tangent_ms_per_step']:.3f} ms/step"
                                if "tangent_ms_per_step" in sa else ""))
+
+    # single precision (float fields and arithmetic, hand-derived partials)
+    eps32 = eps.float()
+    a32 = a_old.float()
+    sig32 = torch.empty_like(eps32)
+    an32 = torch.empty_like(a32)
+
+    def step_32():
+        api.evaluate_f32(eps32, a32, phase, ps.phases, ps.h, 1e-6, ps.max_iter,
+                         sigma_out=sig32, a_out=an32)
+    t32, _, _ = time_calls(step_32, max(3, args.steps // 2), 2, stream)
+    ms_32 = t32 / max(3, args.steps // 2)
+    f32 = {"workload": "same 256^3 batch rounded to float32, FP32 arithmetic, tol 1e-6 (floor "
+                       "at the FP32 rounding level)",
+           "ms_per_step": ms_32, "value": n / (ms_32 * 1e-3), "unit": "updates/s",
+           "bytes_per_point": 4 * 24 + 1, "hbm_gbs": (4 * 24 + 1) * n / (ms_32 * 1e-3) / 1e9,
+           "fp64_over_fp32_time": ms / ms_32}
+    if not args.no_tangent:
+        def step_32t():
+            api.evaluate_f32(eps32, a32, phase, ps.phases, ps.h, 1e-6, ps.max_iter,
+                             sigma_out=sig32, a_out=an32, tangent=True)
+        t32t, _, _ = time_calls(step_32t, max(3, args.steps // 4), 1, stream)
+        f32["tangent_ms_per_step"] = t32t / max(3, args.steps // 4)
+        if "tangent" in out:
+            f32["fp64_over_fp32_time_tangent"] = (out["tangent"]["ms_per_step"] /
+                                                  f32["tangent_ms_per_step"])
+    out["fp32"] = f32
+    log(f"[bench] fp32: {ms_32:.3f} ms/step (fp64 / fp32 = {ms / ms_32:.2f})" +
+        (f", tangent {f32['tangent_ms_per_step']:.3f} ms/step" if "tangent_ms_per_step" in f32
+         else ""))
+    del eps32, a32, sig32, an32
 
     if not args.no_rk23:
         # adaptive explicit Runge-Kutta over one load step of the same batch:

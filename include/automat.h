@@ -438,6 +438,29 @@ int32_t automat_evaluate_rk12(int64_t n, const double *eps_n, const double *eps_
                               int32_t max_steps, double *sigma_out, double *a_out,
                               int32_t *steps_out, uint64_t *nonconverged, void *stream);
 
+/* Single-precision evaluation (Section "Example", paragraph
+ * "Parallelization": single precision works for this material law and pays
+ * off most with tangent). As automat_evaluate_ex with float fields:
+ *   eps_new, a_old  device float [6][n] (in); sigma_out, a_out (may equal
+ *   a_old, or NULL), tangent_out (NULL skips it) device float (out);
+ *   iters_out, nonconverged as automat_evaluate_ex.
+ * Arithmetic is FP32 throughout, with closed-form partials of omega and Psi
+ * (the semi-automatic strategy) and the same Newton solve, line search and
+ * tangent as the FP64 kernels; the convergence test is
+ * ||F||_inf <= max(tol ||a_{n+1} - a_n||_inf, 2^-19 ||eps_new - a_old||_inf),
+ * the floor being the FP32 rounding level of the trial elastic strain, so
+ * a tol below FP32 resolution converges at that floor; an update smaller
+ * than 2^-21 ||a_{n+1} - a_n||_inf (the increment cannot improve in FP32)
+ * also counts as converged. Results agree with
+ * the FP64 evaluation of the same (float) inputs to a few units of FP32
+ * rounding times the conditioning of the step. No flags. Errors as
+ * automat_evaluate_ex. */
+int32_t automat_evaluate_f32(int64_t n, const float *eps_new, const float *a_old,
+                             const uint8_t *phase, const automat_params *params, double h,
+                             double tol, int32_t max_iter, float *sigma_out, float *a_out,
+                             float *tangent_out, int32_t *iters_out, uint64_t *nonconverged,
+                             void *stream);
+
 /* Human-readable text of a return code. */
 const char *automat_strerror(int32_t code);
 

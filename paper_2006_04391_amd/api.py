@@ -23,13 +23,14 @@ def _stream(dev):
     return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
 
 
-def _field(t, name, rows, n=None, dev=None):
+def _field(t, name, rows, n=None, dev=None, dtype=None):
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch tensor")
     if t.device.type != "cuda":
         raise ValueError(f"{name} must be on a GPU (got {t.device}); there is no CPU path")
-    if t.dtype != torch.float64:
-        raise TypeError(f"{name} must be float64")
+    dtype = torch.float64 if dtype is None else dtype
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
     if t.dim() != 2 or t.shape[0] != rows or (n is not None and t.shape[1] != n):
         raise ValueError(f"{name} must have shape ({rows}, n)")
     if not t.is_contiguous():
@@ -103,6 +104,39 @@ def evaluate_conventional(eps, a_old, phase, phases, h=0.1, tol=1e-12, max_iter=
                                                   _ptr(iters), _ptr(count), _stream(dev))
     check("automat_evaluate_conventional", rc)
     return sigma, a_new, iters, count
+
+
+def evaluate_f32(eps, a_old, phase, phases, h=0.1, tol=1e-6, max_iter=50, *, tangent=False,
+                 a_out=None, sigma_out=None, write_a=True, return_iters=False):
+    """Single-precision evaluation (float32 fields and arithmetic). Returns
+    (sigma, a_new) plus the tangent (36, n) if ``tangent`` and (iters,
+    nonconverged_count) if ``return_iters``."""
+    f32 = torch.float32
+    eps = _field(eps, "eps", 6, dtype=f32)
+    n, dev = eps.shape[1], eps.device
+    a_old = _field(a_old, "a_old", 6, n, dev, dtype=f32)
+    phase = _phase_ids(phase, n, dev)
+    params = make_params(phases)
+    sigma = torch.empty_like(eps) if sigma_out is None else _field(sigma_out, "sigma_out", 6, n,
+                                                                   dev, dtype=f32)
+    if write_a:
+        a_new = torch.empty_like(a_old) if a_out is None else _field(a_out, "a_out", 6, n, dev,
+                                                                     dtype=f32)
+    else:
+        a_new = None
+    C = torch.empty((36, n), dtype=f32, device=dev) if tangent else None
+    iters = torch.empty(n, dtype=torch.int32, device=dev) if return_iters else None
+    count = torch.zeros(1, dtype=torch.int64, device=dev) if return_iters else None
+    with torch.cuda.device(dev):
+        rc = load().automat_evaluate_f32(n, _ptr(eps), _ptr(a_old), _ptr(phase),
+                                         ctypes.byref(params), float(h), float(tol), int(max_iter),
+                                         _ptr(sigma), _ptr(a_new), _ptr(C), _ptr(iters),
+                                         _ptr(count), _stream(dev))
+    check("automat_evaluate_f32", rc)
+    out = (sigma, a_new) + ((C,) if tangent else ())
+    if return_iters:
+        out = out + (iters, count)
+    return out
 
 
 def evaluate_rk23(eps_n, eps_new, a_old, phase, phases, h=0.1, atol=1e-6, rtol=1e-3,
