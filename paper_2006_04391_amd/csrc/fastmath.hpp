@@ -106,9 +106,23 @@ AD_FN double rsqrt(double x) {
     return r;
 }
 
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef __attribute__((address_space(4))) const double tab_t;
+// a fresh (opaque) pointer to the table at every call: the compiler cannot
+// hoist the coefficient loads out of the Newton loop and keep them in
+// scalar registers across it; they are reloaded (scalar cache) where used
+AD_FN tab_t *table() {
+    tab_t *T = (tab_t *)fm_tab;
+    asm volatile("" : "+s"(T));
+    return T;
+}
+#else
+AD_FN const double *table() { return fm_tab; }
+#endif
+
 // natural logarithm for finite x > 0
 AD_FN double log(double x) {
-    const double *T = fm_tab;
+    const auto *T = table();
     const bool tiny = x < 0x1p-1000;
     if (tiny) x *= 0x1p+200;
     int k;
@@ -134,7 +148,7 @@ AD_FN double log(double x) {
 
 // exponential
 AD_FN double exp(double x) {
-    const double *T = fm_tab;
+    const auto *T = table();
     if (x < -745.2) return 0.0;
     if (x > 709.8) return HUGE_VAL;
     const double kd = ::rint(x * T[27]);
