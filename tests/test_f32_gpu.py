@@ -102,3 +102,11 @@ def test_f32_invalid_points_and_arguments():
         api.evaluate_f32(eps, a, ph, ps.phases, h=0.0)
     with pytest.raises(TypeError):
         api.evaluate_f32(eps.double(), a, ph, ps.phases)
+
+
+def test_f32_full_size():
+    """The 256^3 fibre batch rounded to float, every point against the FP64
+    oracle on the same inputs."""
+    ps = inputs.points_c1()
+    g, ref, a_old = _run(ps, False)
+    _check(g, ref, ps, a_old, False)

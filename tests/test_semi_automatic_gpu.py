@@ -78,3 +78,15 @@ def test_semi_automatic_many_iterations_and_sigma_flag():
     ref = oracle.evaluate(ps.eps, ps.a_old, ps.phase, ps.phases, h=ps.h, tol=ps.tol,
                           max_iter=ps.max_iter, flags=oracle.SIGMA_CRITERION)
     check(g, ref, ps)
+
+
+def test_semi_automatic_full_size_parity():
+    """The 256^3 fibre batch (the benchmark's launch configuration), every
+    point against the oracle."""
+    from paper_2006_04391_amd import _lib
+    ps = inputs.points_c1()
+    g = _gpu(ps, False, _lib.HAND_PARTIALS)
+    ref = oracle.evaluate(ps.eps, ps.a_old, ps.phase, ps.phases, h=ps.h, tol=ps.tol,
+                          max_iter=ps.max_iter)
+    check(g, ref, ps)
+    assert g["count"] == 0
