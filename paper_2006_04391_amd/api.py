@@ -49,7 +49,8 @@ def _phase_ids(t, n, dev):
 
 
 def evaluate(eps, a_old, phase, phases, h=0.1, tol=1e-12, max_iter=50, *, tangent=False,
-             a_out=None, sigma_out=None, write_a=True, return_iters=False, flags=0):
+             a_out=None, sigma_out=None, tangent_out=None, write_a=True, return_iters=False,
+             flags=0):
     """One implicit-Euler evaluation of every point.
 
     Returns (sigma, a_new) plus the tangent (36, n) if ``tangent`` and
@@ -67,7 +68,11 @@ def evaluate(eps, a_old, phase, phases, h=0.1, tol=1e-12, max_iter=50, *, tangen
         a_new = torch.empty_like(a_old) if a_out is None else _field(a_out, "a_out", 6, n, dev)
     else:
         a_new = None
-    C = torch.empty((36, n), dtype=torch.float64, device=dev) if tangent else None
+    if tangent:
+        C = (torch.empty((36, n), dtype=torch.float64, device=dev) if tangent_out is None
+             else _field(tangent_out, "tangent_out", 36, n, dev))
+    else:
+        C = None
     iters = torch.empty(n, dtype=torch.int32, device=dev) if return_iters else None
     count = torch.zeros(1, dtype=torch.int64, device=dev) if return_iters else None
     lib = load()
@@ -107,7 +112,7 @@ def evaluate_conventional(eps, a_old, phase, phases, h=0.1, tol=1e-12, max_iter=
 
 
 def evaluate_f32(eps, a_old, phase, phases, h=0.1, tol=1e-6, max_iter=50, *, tangent=False,
-                 a_out=None, sigma_out=None, write_a=True, return_iters=False):
+                 a_out=None, sigma_out=None, tangent_out=None, write_a=True, return_iters=False):
     """Single-precision evaluation (float32 fields and arithmetic). Returns
     (sigma, a_new) plus the tangent (36, n) if ``tangent`` and (iters,
     nonconverged_count) if ``return_iters``."""
@@ -124,7 +129,11 @@ def evaluate_f32(eps, a_old, phase, phases, h=0.1, tol=1e-6, max_iter=50, *, tan
                                                                      dtype=f32)
     else:
         a_new = None
-    C = torch.empty((36, n), dtype=f32, device=dev) if tangent else None
+    if tangent:
+        C = (torch.empty((36, n), dtype=f32, device=dev) if tangent_out is None
+             else _field(tangent_out, "tangent_out", 36, n, dev, dtype=f32))
+    else:
+        C = None
     iters = torch.empty(n, dtype=torch.int32, device=dev) if return_iters else None
     count = torch.zeros(1, dtype=torch.int64, device=dev) if return_iters else None
     with torch.cuda.device(dev):
