@@ -71,3 +71,45 @@ def test_package_does_not_import_oracle():
             if fn.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in text and "oracle_" not in text, fn
+
+
+def test_struct_layouts_match_the_c_header(tmp_path):
+    """sizeof / offsetof of every struct of include/automat.h, compiled as C,
+    against the ctypes mirrors of the binding."""
+    import os
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    inc = os.path.join(os.path.dirname(__file__), "..", "include")
+    checks = {
+        "automat_phase": ("Phase", ["kind", "E", "nu", "H", "sigma_y", "sigma0", "eps0", "n"]),
+        "automat_params": ("Params", ["n_phases", "phase"]),
+        "automat_ms_options": ("MsOptions", ["tol", "max_iter", "fixed_iter", "lambda0", "mu0",
+                                             "newton_tol", "newton_max_iter", "ref_update",
+                                             "warm_start", "reserved"]),
+        "automat_request": ("Request", [f[0] for f in _lib.Request._fields_]),
+        "automat_result": ("Result", [f[0] for f in _lib.Result._fields_]),
+        "automat_server_stats_t": ("ServerStats", [f[0] for f in _lib.ServerStats._fields_]),
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "automat.h"', "int main(void) {"]
+    for cname, (_, fields) in checks.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f in fields:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", f"-I{inc}", str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                               text=True).stdout.splitlines():
+        parts = line.split()
+        got[tuple(parts[:-1])] = int(parts[-1])
+    for cname, (pyname, fields) in checks.items():
+        cls = getattr(_lib, pyname)
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f in fields:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
