@@ -236,3 +236,21 @@ def test_mixed_invalid_arguments():
         ms.step_mixed(torch.zeros(64, dtype=torch.uint8, device="cuda"), [1e-3] + [0] * 5, 0.1,
                       z, z.clone(), 64)
     ms.close()
+
+
+def test_warm_start_does_not_change_the_solution():
+    """Warm-started and cold per-point Newton solves converge to the same
+    load-step solutions (within the fixed-point tolerance), without
+    unconverged point solves, through yield and load reversal."""
+    N_ = 12
+    phase = inputs.fibre_phase(N_, seed=5, radius=1.0, length=10.0, vol_frac=0.102)
+    ph = inputs.paper_phases()
+    loads = [[e, 0, 0, 0, 0, 0] for e in (1e-3, 3e-3, 4e-3, 1e-3, -2e-3)]
+    tol = 1e-8
+    runs = {w: _gpu_run_mixed((N_,) * 3, phase, ph, loads, 0.5, UNIAXIAL, tol=tol, max_iter=3000,
+                              warm_start=w, ref_update=True) for w in (True, False)}
+    for w, c in zip(runs[True], runs[False]):
+        assert w["failures"] == 0 and c["failures"] == 0
+        scale = np.abs(c["sigma"]).max()
+        assert np.abs(w["sigma"] - c["sigma"]).max() <= 1e-5 * scale
+        np.testing.assert_allclose(w["sigma_mean"][0], c["sigma_mean"][0], rtol=1e-6)
