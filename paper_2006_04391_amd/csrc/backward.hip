@@ -95,16 +95,16 @@ __global__ __launch_bounds__(kBlock) void gsm_backward_kernel(const BackArgs arg
             for (int c = 0; c < 6; ++c) abar[c] = ga[c] + ae[c];
             double gp[AUTOMAT_NPAR] = {0, 0, 0, 0, 0, 0, 0};
             if (Model::flows(prm)) {
-                double A[6], M[21], idg[6];
+                double A[6], M[21];
                 Model::gen_stress(prm, eps, a, A);
                 Model::psi_hess(prm, A, M);
 #pragma unroll
                 for (int c = 0; c < 21; ++c) M[c] = pc.Kinv[c] + h * M[c];
-                la::cholesky6(M, idg);
+                la::cholesky6(M);
                 la::symv6(pc.Kinv, abar, r);
 #pragma unroll
                 for (int c = 0; c < 6; ++c) w[c] = r[c];
-                la::chol_solve6(M, idg, w);
+                la::chol_solve6(M, w);
                 double hw[6];
 #pragma unroll
                 for (int c = 0; c < 6; ++c) hw[c] = h * w[c];

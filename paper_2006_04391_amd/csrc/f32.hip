@@ -72,7 +72,7 @@ __device__ void build_f32_const(const MSGSM::Phase &raw, F32Const &c) {
     c.coef = (float)p.coef;
     c.pq = (float)p.pq;
     c.n = (float)p.n;
-    double C[6][6], Kaa[21], L[21], idg[6], Kinv[21];
+    double C[6][6], Kaa[21], L[21], Kinv[21];
     for (int i = 0; i < 6; ++i)
         for (int j = 0; j < 6; ++j) {
             double v = 0.0;
@@ -88,11 +88,11 @@ __device__ void build_f32_const(const MSGSM::Phase &raw, F32Const &c) {
             c.K[pkf(i, j)] = (float)Kaa[la::pk(i, j)];
             c.Cee[pkf(i, j)] = (float)C[i][j];
         }
-    la::cholesky6(L, idg);
+    la::cholesky6(L);
     for (int j = 0; j < 6; ++j) {
         double col[6] = {0, 0, 0, 0, 0, 0};
         col[j] = 1.0;
-        la::chol_solve6(L, idg, col);
+        la::chol_solve6(L, col);
         for (int i = j; i < 6; ++i) Kinv[la::pk(i, j)] = col[i];
     }
     for (int i = 0; i < 21; ++i) c.Kinv[i] = (float)Kinv[i];

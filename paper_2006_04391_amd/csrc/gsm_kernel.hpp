@@ -57,6 +57,20 @@ __device__ __forceinline__ void count_failures(unsigned long long *counter, bool
 // updates, or -1 (not converged within max_iter, or invalid input). Outputs
 // sigma, a_{n+1} and, if TANGENT, the packed consistent tangent C[21].
 // WARM: D may be non-zero on entry (otherwise it must be zero).
+//
+// Without TANGENT the solve keeps the Cholesky factor of the last Newton
+// matrix and may take the next step with it (a simplified-Newton step),
+// but only where that step is predicted to end the iteration: with
+// rho = ||F_k|| / ||F_{k-1}|| the observed contraction of the last step, a
+// step with a factor one step old leaves a residual of about
+// 2 rho ||F_k||, and it is taken only if that meets the stopping test.
+// Otherwise the Newton matrix is rebuilt at the current point, as in
+// Newton's method. Likewise, a trial point is evaluated to first order
+// (no Psi'') when the step changes the thermodynamic force A by less than
+// 1e-3 relative: the step is then all but exact, and the next one, if any,
+// is expected to reuse the factor. Both rules only skip work that the
+// iteration would not use; the iterates are Newton's wherever the
+// prediction fails.
 template <class Model, bool TANGENT, int S = kBlock, bool WARM = false>
 __device__ __forceinline__ int solve_point(const PhaseConst<Model> &pc, bool valid, const double *eps,
                                            const double *an, double h, double tol, int max_iter,
@@ -69,10 +83,15 @@ __device__ __forceinline__ int solve_point(const PhaseConst<Model> &pc, bool val
 #pragma unroll
         for (int c = 0; c < 6; ++c) D[c] = 0.0;
     }
+    constexpr bool kReuse = !TANGENT;
     Resid2 cur;
     // cur.M holds the Newton matrix of the current point only when have_M:
     // a trial predicted to end the iteration is evaluated to first order.
-    bool have_M = true;
+    // Otherwise (after a first-order trial) it holds the Cholesky factor of
+    // the Newton matrix of an earlier iterate, valid when have_L; fprev is
+    // ||F||_inf where the last step was computed.
+    bool have_M = true, have_L = false;
+    double fprev = 0.0;
     // merit value Phi(D) = D.K.D / 2 + h Psi(A(D)), the scale of the line
     // search's round-off allowance
     double phi = 0.0;
@@ -140,19 +159,32 @@ __device__ __forceinline__ int solve_point(const PhaseConst<Model> &pc, bool val
         }
         if (__ballot(!done) == 0) break;
         if (!done && !have_M) {
-            // the last trial was expected to converge and did not
-            newton_matrix<Model>(prm, pc.Kinv, h, cur);
+            // a first-order trial did not end the iteration: take the next
+            // step with the factor at hand if it is predicted to be the
+            // last, else build the Newton matrix of the current point
+            bool reuse = false;
+            if constexpr (kReuse) {
+                const double fn = la::norm_inf6(cur.F);
+                reuse = have_L &&
+                        2.0 * fn * fn <= fprev * fmax(tol * la::norm_inf6(D), floor_F);
+            }
+            if (!reuse) {
+                newton_matrix<Model>(prm, pc.Kinv, h, cur);
+                have_M = true;
+            }
             lds_reload_point();
         }
         bool first_order = false;
         double y[6], delta[6];
         if (!done) {
-            // Cholesky factor of M = K^-1 + h Psi'' (from the last residual)
-            double idg[6];
-            const bool spd = la::cholesky6(cur.M, idg);
+            // Cholesky factor of M = K^-1 + h Psi'' (from the last residual),
+            // unless the previous factor is reused
+            bool spd = true;
+            if (have_M) spd = la::cholesky6(cur.M);
+            have_L = spd;
 #pragma unroll
             for (int c = 0; c < 6; ++c) y[c] = cur.F[c];
-            la::chol_solve6(cur.M, idg, y);
+            la::chol_solve6(cur.M, y);
             lds_reload_point();
             if (!spd) {
                 done = true;
@@ -175,6 +207,7 @@ __device__ __forceinline__ int solve_point(const PhaseConst<Model> &pc, bool val
                     if (no_flow || k == kWarmRestart) {
 #pragma unroll
                         for (int c = 0; c < 6; ++c) delta[c] = D[c];
+                        have_L = false;
                     }
                 }
                 // quadratic convergence: a step this small relative to the
@@ -186,6 +219,12 @@ __device__ __forceinline__ int solve_point(const PhaseConst<Model> &pc, bool val
                     nn = fmax(nn, fabs(D[c] - delta[c]));
                 }
                 first_order = dn <= 1e-3 * nn;
+                if constexpr (kReuse) {
+                    fprev = la::norm_inf6(cur.F);
+                    // the step moves A by K delta = y
+                    first_order = first_order ||
+                                  (have_L && la::norm_inf6(y) <= 1e-3 * la::norm_inf6(cur.A));
+                }
             }
         }
         // one kind of trial evaluation for the whole wave
@@ -241,8 +280,8 @@ __device__ __forceinline__ int solve_point(const PhaseConst<Model> &pc, bool val
             // M at the converged point came with the last residual, unless
             // that was a first-order trial
             if (!have_M) newton_matrix<Model>(prm, pc.Kinv, h, cur);
-            double *M = cur.M, idg[6];
-            la::cholesky6(M, idg);
+            double *M = cur.M;
+            la::cholesky6(M);
             // C = C0 + R^T M^-1 R one column of M^-1 R at a time (lower
             // triangle only: the packed result is symmetric exactly)
 #pragma unroll
@@ -252,7 +291,7 @@ __device__ __forceinline__ int solve_point(const PhaseConst<Model> &pc, bool val
                 double x[6];
 #pragma unroll
                 for (int r = 0; r < 6; ++r) x[r] = pc.R[r * 6 + j];
-                la::chol_solve6(M, idg, x);
+                la::chol_solve6(M, x);
 #pragma unroll
                 for (int r = j; r < 6; ++r) {
                     double acc = C[la::pk(r, j)];

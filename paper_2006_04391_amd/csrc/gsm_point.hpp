@@ -63,19 +63,19 @@ AD_FN bool build_phase_const(const typename Model::Phase &p, PhaseConst<Model> &
     Model::derive(pc.prm);
     double Kaa[21], Kae[6][6], Kee[21];
     Model::omega_hessian(pc.prm, Kaa, Kae, Kee);
-    double L[21], idg[6];
+    double L[21];
 #pragma unroll
     for (int i = 0; i < 21; ++i) {
         L[i] = Kaa[i];
         pc.K[i] = Kaa[i];
         pc.Cee[i] = Kee[i];
     }
-    const bool ok = la::cholesky6(L, idg);
+    const bool ok = la::cholesky6(L);
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
         double col[6] = {0, 0, 0, 0, 0, 0};
         col[j] = 1.0;
-        la::chol_solve6(L, idg, col);
+        la::chol_solve6(L, col);
 #pragma unroll
         for (int i = j; i < 6; ++i) pc.Kinv[la::pk(i, j)] = col[i];
     }

@@ -15,9 +15,11 @@ namespace la {
 AD_FN constexpr int pk(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
 
 // In-place Cholesky factorization M = L L^T of a packed SPD matrix. On
-// return the packed array holds L and idg[j] = 1 / L_jj. Returns false if a
-// pivot is not positive (matrix not positive definite or not finite).
-AD_FN bool cholesky6(double *L, double *idg) {
+// return the packed array holds the strictly lower part of L and, on the
+// diagonal, the inverse pivots 1 / L_jj (the solves below multiply by them;
+// L_jj itself is never needed). Returns false if a pivot is not positive
+// (matrix not positive definite or not finite).
+AD_FN bool cholesky6(double *L) {
     bool ok = true;
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
@@ -26,8 +28,7 @@ AD_FN bool cholesky6(double *L, double *idg) {
         for (int k = 0; k < j; ++k) d -= L[pk(j, k)] * L[pk(j, k)];
         ok = ok && (d > 0.0);
         const double inv = fm::rsqrt(d);
-        L[pk(j, j)] = d * inv;
-        idg[j] = inv;
+        L[pk(j, j)] = inv;
 #pragma unroll
         for (int i = j + 1; i < 6; ++i) {
             double s = L[pk(i, j)];
@@ -39,32 +40,32 @@ AD_FN bool cholesky6(double *L, double *idg) {
     return ok;
 }
 
-// Solve L z = b in place.
-AD_FN void forward6(const double *L, const double *idg, double *b) {
+// Solve L z = b in place (L as returned by cholesky6).
+AD_FN void forward6(const double *L, double *b) {
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
         double s = b[i];
 #pragma unroll
         for (int k = 0; k < i; ++k) s -= L[pk(i, k)] * b[k];
-        b[i] = s * idg[i];
+        b[i] = s * L[pk(i, i)];
     }
 }
 
-// Solve L^T y = z in place.
-AD_FN void backward6(const double *L, const double *idg, double *b) {
+// Solve L^T y = z in place (L as returned by cholesky6).
+AD_FN void backward6(const double *L, double *b) {
 #pragma unroll
     for (int i = 5; i >= 0; --i) {
         double s = b[i];
 #pragma unroll
         for (int k = i + 1; k < 6; ++k) s -= L[pk(k, i)] * b[k];
-        b[i] = s * idg[i];
+        b[i] = s * L[pk(i, i)];
     }
 }
 
-// Solve (L L^T) x = b in place.
-AD_FN void chol_solve6(const double *L, const double *idg, double *b) {
-    forward6(L, idg, b);
-    backward6(L, idg, b);
+// Solve (L L^T) x = b in place (L as returned by cholesky6).
+AD_FN void chol_solve6(const double *L, double *b) {
+    forward6(L, b);
+    backward6(L, b);
 }
 
 // y = S x for packed symmetric S.

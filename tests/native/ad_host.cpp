@@ -88,10 +88,10 @@ void ad_generic(const double *x, double *val, double *g, double *H) {
 
 // Symmetric 6x6 Cholesky solve (packed lower input).
 int la_solve(const double *Mp, double *b) {
-    double L[21], idg[6];
+    double L[21];
     for (int i = 0; i < 21; ++i) L[i] = Mp[i];
-    const bool ok = la::cholesky6(L, idg);
-    la::chol_solve6(L, idg, b);
+    const bool ok = la::cholesky6(L);
+    la::chol_solve6(L, b);
     return ok ? 0 : -1;
 }
 
