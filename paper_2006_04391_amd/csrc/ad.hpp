@@ -550,23 +550,38 @@ struct Pow : Expr<Pow<U, P>> {
         u.prep();
         p.prep();
         const double uv = u.v(), pv = p.v();
-        if (uv > 0.0) {
+        // a constant integer exponent >= 1: the partials in u by products
+        // (the exponent carries no derivative, so log u is not needed).
+        // Every branch fills locals and the members are assigned once, so
+        // the node stays in registers.
+        const bool by_products =
+            std::is_same_v<P, Cst> && uv > 0.0 && pv >= 1.0 && fm::small_int_exponent(pv);
+        double Y = 0.0, Yu = 0.0, Yp = 0.0, Yuu = 0.0, Yup = 0.0, Ypp = 0.0;
+        if (by_products) {
+            const double w2 = pv == 1.0 ? 0.0 : fm::pow_int(uv, (int)pv - 2);  // u^(p-2)
+            const double w1 = pv == 1.0 ? 1.0 : w2 * uv;                       // u^(p-1)
+            Y = w1 * uv;
+            Yu = pv * w1;
+            Yuu = (pv - 1.0) * pv * w2;
+        } else if (uv > 0.0) {
             const double lu = fm::log(uv);
             const double iu = fm::rcp(uv);
-            y = fm::exp(pv * lu);
-            yu = pv * y * iu;
-            yp = y * lu;
-            yuu = (pv - 1.0) * yu * iu;
-            yup = yu * lu + y * iu;
-            ypp = yp * lu;
+            Y = fm::exp(pv * lu);
+            Yu = pv * Y * iu;
+            Yp = Y * lu;
+            Yuu = (pv - 1.0) * Yu * iu;
+            Yup = Yu * lu + Y * iu;
+            Ypp = Yp * lu;
         } else {
-            y = 0.0;
-            yp = 0.0;
-            yu = pv == 1.0 ? 1.0 : 0.0;
-            yuu = pv == 2.0 ? 2.0 : 0.0;
-            yup = 0.0;
-            ypp = 0.0;
+            Yu = pv == 1.0 ? 1.0 : 0.0;
+            Yuu = pv == 2.0 ? 2.0 : 0.0;
         }
+        y = Y;
+        yu = Yu;
+        yp = Yp;
+        yuu = Yuu;
+        yup = Yup;
+        ypp = Ypp;
     }
     AD_FN double v() const { return y; }
     template <class Dir>

@@ -50,7 +50,7 @@ struct ConvArgs {
 };
 
 // x^p for x > 0
-__device__ __forceinline__ double powp(double x, double p) { return fm::exp(p * fm::log(x)); }
+__device__ __forceinline__ double powp(double x, double p) { return fm::pow_pos(x, p); }
 
 __global__ __launch_bounds__(kConvBlock) void conventional_kernel(const ConvArgs args) {
     const int64_t n = args.n;

@@ -74,7 +74,7 @@ struct MSGSMHand : MSGSM {
                 a2 = 0.0;
                 return true;
             }
-            const double uc1 = fm::exp((c - 1.0) * fm::log(u));  // u^(c - 1)
+            const double uc1 = fm::pow_pos(u, c - 1.0);  // u^(c - 1)
             val = p.coef * uc1 * u;
             a1 = p.coef * c * uc1 * k;
             a2 = p.coef * c * (c - 1.0) * uc1 / u * k * k;
@@ -84,7 +84,7 @@ struct MSGSMHand : MSGSM {
         const double x = (q - p.sy) * p.is0;
         if (!(x > 0.0)) return false;
         const double n = p.pq - 1.0;
-        const double xn1 = fm::exp((n - 1.0) * fm::log(x));  // x^(n - 1)
+        const double xn1 = fm::pow_pos(x, n - 1.0);  // x^(n - 1)
         const double xn = xn1 * x;
         val = p.coef * xn * x;
         // dPsi/dq = coef pq x^n / sigma0 = eps0 x^n, d2Psi/dq2 = eps0 n x^(n-1) / sigma0;

@@ -36,6 +36,22 @@ void fm_vec(int which, const double *x, double *y, int64_t n) {
     }
 }
 
+void fm_pow(const double *x, const double *e, double *y, int64_t n) {
+    for (int64_t i = 0; i < n; ++i) y[i] = fm::pow_pos(x[i], e[i]);
+}
+
+// pow node of the AD layer with a constant exponent: value, first and
+// second derivative in u
+void ad_pow_const(const double *u, double e, double *val, double *d1, double *d2, int64_t n) {
+    for (int64_t i = 0; i < n; ++i) {
+        ad::Var<0> a(u[i]);
+        ad::HessRows<1, 1, 0> acc;
+        val[i] = ad::sweep2(pow(a, e), ad::UnitDirs<1, 0>{}, acc);
+        d1[i] = acc.g[0];
+        d2[i] = acc.H[0][0];
+    }
+}
+
 // Psi, f = dPsi/dA (first-order sweep) and Psi'' (one vector sweep).
 void ad_psi(const double *row, const double *A, double *psi, double *f, double *Hp, double *f2) {
     M::Phase p = phase_from_row(row);

@@ -31,6 +31,8 @@ def lib():
     L = ctypes.CDLL(OUT)
     dp = ctypes.POINTER(ctypes.c_double)
     L.fm_vec.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int64]
+    L.fm_pow.argtypes = [dp, dp, dp, ctypes.c_int64]
+    L.ad_pow_const.argtypes = [dp, ctypes.c_double, dp, dp, dp, ctypes.c_int64]
     L.ad_psi.argtypes = [dp] * 6
     L.ad_omega.argtypes = [dp] * 8
     L.ad_params.argtypes = [dp] * 10
@@ -73,11 +75,52 @@ def test_fast_log_exp_rcp_rsqrt_accuracy(lib):
     assert ulps(fm(lib, 3, r), 1.0 / np.sqrt(r)).max() <= 2
 
 
-@pytest.mark.parametrize("preset", ["config", "paper", "n1", "n1_threshold"])
+def test_pow_small_integer_exponents_by_products(lib):
+    """x^e: integer e in 0..8 by products, any other e by exp(e log x)."""
+    rng = np.random.default_rng(3)
+    x = 10.0 ** rng.uniform(-3, 3, 20000)
+    for e in range(9):
+        ee = np.full_like(x, float(e))
+        y = np.empty_like(x)
+        lib.fm_pow(P(x), P(ee), P(y), x.size)
+        # at most e - 1 rounded products: below e - 1 units in the last place
+        assert ulps(y, np.power(x, float(e))).max() <= max(e - 1, 1), e
+    for e in (0.5, 2.5, 3.6, -1.5, 8.5, 9.0):
+        ee = np.full_like(x, e)
+        y = np.empty_like(x)
+        lib.fm_pow(P(x), P(ee), P(y), x.size)
+        ref = np.power(x, e)
+        assert (np.abs(y - ref) / ref).max() <= 1e-14, e
+
+
+@pytest.mark.parametrize("e", [1.0, 2.0, 3.0, 4.0, 5.0, 6.0, 7.0, 8.0, 2.5, 3.6, 9.0])
+def test_ad_pow_constant_exponent_derivatives(lib, e):
+    """Value and first two derivatives of the AD layer's power with a
+    constant exponent against e u^(e-1) and e (e-1) u^(e-2), and at u = 0."""
+    rng = np.random.default_rng(4)
+    u = np.concatenate([10.0 ** rng.uniform(-2, 2, 2000), [0.0]])
+    val, d1, d2 = f64(u.size), f64(u.size), f64(u.size)
+    lib.ad_pow_const(P(u), e, P(val), P(d1), P(d2), u.size)
+    p = u[:-1]
+    np.testing.assert_allclose(val[:-1], p ** e, rtol=1e-14, atol=0)
+    np.testing.assert_allclose(d1[:-1], e * p ** (e - 1), rtol=1e-14, atol=0)
+    np.testing.assert_allclose(d2[:-1], e * (e - 1) * p ** (e - 2), rtol=1e-14, atol=0)
+    assert val[-1] == 0.0
+    assert d1[-1] == (1.0 if e == 1.0 else 0.0)
+    assert d2[-1] == (2.0 if e == 2.0 else 0.0)
+
+
+@pytest.mark.parametrize("preset", ["config", "paper", "n1", "n1_threshold", "n2", "n3",
+                                    "n5_threshold", "n7_threshold"])
 def test_ad_force_potential_matches_hand_derivatives(lib, preset):
-    ph = {"config": inputs.config_phases()[0], "paper": inputs.paper_phases()[0],
-          "n1": dict(inputs.config_phases()[0], n=1.0, eps0=0.3),
-          "n1_threshold": dict(inputs.config_phases()[0], n=1.0, sigma_y=3.0)}[preset]
+    cfg = inputs.config_phases()[0]
+    ph = {"config": cfg, "paper": inputs.paper_phases()[0],
+          "n1": dict(cfg, n=1.0, eps0=0.3),
+          "n1_threshold": dict(cfg, n=1.0, sigma_y=3.0),
+          "n2": dict(cfg, n=2.0),                      # Psi ~ u^1.5: exp/log path
+          "n3": dict(cfg, n=3.0),                      # Psi ~ u^2: products
+          "n5_threshold": dict(cfg, sigma_y=3.0),      # x^6: products
+          "n7_threshold": dict(cfg, n=7.0, sigma_y=3.0)}[preset]   # x^8: products
     row = inputs.phases_array([ph])[0]
     rng = np.random.default_rng(1)
     for _ in range(200):
