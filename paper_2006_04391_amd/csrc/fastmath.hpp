@@ -7,9 +7,13 @@
 // instruction count.
 //
 // Methods (textbook, written from the mathematics):
-//  * rcp / rsqrt: the hardware estimate (v_rcp_f64 / v_rsq_f64) refined by
-//    two Newton-Raphson steps, r <- r + r (1 - x r) and
-//    r <- r + r/2 (1 - x r^2);
+//  * rcp / rsqrt: the hardware estimate (v_rcp_f64 / v_rsq_f64, relative
+//    error below 2^-22) refined by one third-order step: with e = 1 - x r
+//    (rcp) or e = 1 - x r^2 (rsqrt), 1/x = r / (1 - e) = r (1 + e + e^2 + ...)
+//    and 1/sqrt(x) = r (1 - e)^(-1/2) = r (1 + e/2 + 3e^2/8 + ...), each
+//    truncated after e^2 (truncation below 2^-64); three dependent
+//    operations after the estimate instead of the four to six of two
+//    Newton-Raphson steps;
 //  * log: x = 2^k m with m in [sqrt(1/2), sqrt(2)), s = (m - 1)/(m + 1),
 //    log m = 2 atanh s = 2 (s + s^3/3 + s^5/5 + ...) summed to s^23
 //    (|s| <= 0.1716, truncation < 1e-17), log x = k ln2 + log m with ln2
@@ -89,22 +93,16 @@ AD_FN double rsq_estimate(double x) {
 
 // 1 / x for finite x != 0
 AD_FN double rcp(double x) {
-    double r = rcp_estimate(x);
-    double e = ::fma(-x, r, 1.0);
-    r = ::fma(r, e, r);
-    e = ::fma(-x, r, 1.0);
-    return ::fma(r, e, r);
+    const double r = rcp_estimate(x);
+    const double e = ::fma(-x, r, 1.0);
+    return ::fma(r, ::fma(e, e, e), r);
 }
 
 // 1 / sqrt(x) for finite x > 0
 AD_FN double rsqrt(double x) {
-    double r = rsq_estimate(x);
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const double e = ::fma(-x, r * r, 1.0);
-        r = ::fma(0.5 * r, e, r);
-    }
-    return r;
+    const double r = rsq_estimate(x);
+    const double e = ::fma(-x, r * r, 1.0);
+    return ::fma(r * e, ::fma(0.375, e, 0.5), r);
 }
 
 #if defined(__HIP_DEVICE_COMPILE__)
