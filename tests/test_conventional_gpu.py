@@ -22,6 +22,10 @@ def _case(preset, n):
         ph = inputs.config_phases()
         ph[0] = dict(ph[0], H=900.0, sigma_y=4.0, eps0=0.5, n=3.3)
         ps = inputs.points_random(n, seed=33, phases=ph, e11=3e-2, std=5e-3, a_std=2e-3)
+    elif preset == "threshold_int":                 # x^5, x^4 by products
+        ph = inputs.config_phases()
+        ph[0] = dict(ph[0], H=400.0, sigma_y=6.0, eps0=0.3)
+        ps = inputs.points_random(n, seed=35, phases=ph, e11=2e-2, std=4e-3, a_std=1e-3)
     else:
         ph = inputs.config_phases()
         ph[0] = dict(ph[0], n=1.0, eps0=0.1)
@@ -30,7 +34,7 @@ def _case(preset, n):
 
 
 @pytest.mark.parametrize("preset,n", [("config", 4133), ("paper", 1025), ("hardening", 999),
-                                      ("linear", 300)])
+                                      ("linear", 300), ("threshold_int", 700)])
 def test_radial_return_matches_the_automatic_solution(preset, n):
     from paper_2006_04391_amd import api
     ps = _case(preset, n)

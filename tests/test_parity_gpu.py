@@ -78,9 +78,11 @@ def test_c0_4096_points(tangent):
 
 
 @pytest.mark.parametrize("preset,n", [("config", 256 * 5 + 37), ("paper", 256 * 3 + 1),
-                                      ("hardening", 999), ("linear", 300)])
+                                      ("hardening", 999), ("linear", 300),
+                                      ("threshold_int", 700), ("n3", 513)])
 def test_random_presets_ragged(preset, n):
-    """Several tiles plus a ragged tail, in the nonlinear regimes."""
+    """Several tiles plus a ragged tail, in the nonlinear regimes (integer
+    exponents take the power by products, the others exp/log)."""
     if preset == "config":
         ps = inputs.points_random(n, seed=21, e11=2e-2, std=3e-3, a_std=1e-3)
         ps.phases = [dict(ps.phases[0], eps0=0.2), ps.phases[1]]
@@ -91,10 +93,18 @@ def test_random_presets_ragged(preset, n):
         ph = inputs.config_phases()
         ph[0] = dict(ph[0], H=900.0, sigma_y=4.0, eps0=0.5, n=3.3)
         ps = inputs.points_random(n, seed=23, phases=ph, e11=3e-2, std=5e-3, a_std=2e-3)
-    else:
+    elif preset == "linear":
         ph = inputs.config_phases()
         ph[0] = dict(ph[0], n=1.0, eps0=0.1)
         ps = inputs.points_random(n, seed=24, phases=ph, e11=3e-2, std=5e-3, a_std=2e-3)
+    elif preset == "threshold_int":                 # x^6 with a yield threshold
+        ph = inputs.config_phases()
+        ph[0] = dict(ph[0], H=400.0, sigma_y=6.0, eps0=0.3)
+        ps = inputs.points_random(n, seed=28, phases=ph, e11=2e-2, std=4e-3, a_std=1e-3)
+    else:                                           # n = 3: u^2 without threshold
+        ph = inputs.config_phases()
+        ph[0] = dict(ph[0], n=3.0, eps0=0.05)
+        ps = inputs.points_random(n, seed=29, phases=ph, e11=2e-2, std=4e-3, a_std=1e-3)
     for tangent in (False, True):
         g, ref = run_both(ps, tangent=tangent)
         check(g, ref, ps, tangent)

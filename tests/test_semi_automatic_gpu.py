@@ -41,6 +41,10 @@ def _presets():
     ph[0] = dict(ph[0], n=1.0, eps0=0.1)
     out.append(("linear", inputs.points_random(300, seed=34, phases=ph, e11=3e-2, std=5e-3,
                                                a_std=2e-3)))
+    ph = inputs.config_phases()
+    ph[0] = dict(ph[0], H=400.0, sigma_y=6.0, eps0=0.3)      # x^6 by products
+    out.append(("threshold_int", inputs.points_random(700, seed=35, phases=ph, e11=2e-2,
+                                                      std=4e-3, a_std=1e-3)))
     return out
 
 
