@@ -403,6 +403,7 @@ def main():
         # the strain ramps from 0.8 eps to eps (the last step of a 5-step path)
         eps_n = 0.8 * eps
         a_rk = torch.empty_like(a_old)
+        tan_rk = None
         for pair, fn in (("rk23", api.evaluate_rk23), ("rk12", api.evaluate_rk12)):
             steps_rk = {}
 
@@ -420,7 +421,23 @@ def main():
                          "accepted_steps_histogram": {int(k): int(v) for k, v in
                                                       zip(*np.unique(st, return_counts=True))}}
             log(f"[bench] {pair}: {ms_rk:.3f} ms/step")
-        del eps_n, a_rk
+            # with the consistent tangent (the sensitivity system integrated
+            # alongside and inside the error measure)
+            if tan_rk is None:
+                tan_rk = torch.empty((36, n), dtype=torch.float64, device=dev)
+
+            def step_rk_t():
+                r = fn(eps_n, eps, a_old, phase, ps.phases, h=ps.h, tangent=True,
+                       sigma_out=sigma, a_out=a_rk, tangent_out=tan_rk)
+                steps_rk["tan"] = r[3]
+            tt_rk, _, _ = time_calls(step_rk_t, 3, 1, stream)
+            ms_rk_t = tt_rk / 3
+            st_t = steps_rk["tan"].cpu().numpy()
+            out[pair]["tangent_ms_per_step"] = ms_rk_t
+            out[pair]["tangent_accepted_steps_histogram"] = {
+                int(k): int(v) for k, v in zip(*np.unique(st_t, return_counts=True))}
+            log(f"[bench] {pair} with tangent: {ms_rk_t:.3f} ms/step")
+        del eps_n, a_rk, tan_rk
 
     if args.ms_steps > 0:
         out["ms"] = ms_bench(args.ms_steps)

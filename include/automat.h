@@ -419,7 +419,7 @@ int32_t automat_evaluate_conventional(int64_t n, const double *eps_new, const do
  *                          *nonconverged (device uint64, or NULL).
  * atol >= 0, rtol > 0 (MATLAB's defaults are 1e-6 and 1e-3), max_steps >= 1.
  * Stream-ordered, asynchronous. The consistent tangent of this scheme is
- * not computed here. */
+ * computed by automat_evaluate_rk23_ex. */
 int32_t automat_evaluate_rk23(int64_t n, const double *eps_n, const double *eps_new,
                               const double *a_old, const uint8_t *phase,
                               const automat_params *params, double h, double atol, double rtol,
@@ -437,6 +437,35 @@ int32_t automat_evaluate_rk12(int64_t n, const double *eps_n, const double *eps_
                               const automat_params *params, double h, double atol, double rtol,
                               int32_t max_steps, double *sigma_out, double *a_out,
                               int32_t *steps_out, uint64_t *nonconverged, void *stream);
+
+/* The adaptive schemes above with their consistent tangent (Section
+ * "Rosenbrock and Runge-Kutta Schemes with Adaptive Step Size", the theorem
+ * on differentiating an integration step; Section "Error Control" for the
+ * error measure). The sensitivity Y = d a / d eps_new (6x6, Y = 0 at the
+ * start of the step) follows Y' = Psi''(A) ((t/h) C - K Y), with C the
+ * elastic stiffness and K = d^2 omega / da^2, and is advanced with the same
+ * stages and accepted steps as a; the error measure of a step is the rms over
+ * 42 components: the six stresses as above and the 36 entries of
+ * T = C ((t/h) I - Y), scaled the same way, so the tangent's accuracy also
+ * controls the step size (steps_out can exceed that of the plain call). On
+ * return tangent_out holds C_{n+1} = d sigma / d eps_new = C (I - Y(h)),
+ * device [36][n], row-major 6x6 per point (entry (r, c) at [(6 r + c) n + i]);
+ * C for points without flow, NaN for invalid points. tangent_out must not
+ * overlap the other arrays; NULL gives the plain evaluation. Other
+ * arguments, layout, ownership and errors as automat_evaluate_rk23 (rk23_ex)
+ * and automat_evaluate_rk12 (rk12_ex). */
+int32_t automat_evaluate_rk23_ex(int64_t n, const double *eps_n, const double *eps_new,
+                                 const double *a_old, const uint8_t *phase,
+                                 const automat_params *params, double h, double atol,
+                                 double rtol, int32_t max_steps, double *sigma_out,
+                                 double *a_out, double *tangent_out, int32_t *steps_out,
+                                 uint64_t *nonconverged, void *stream);
+int32_t automat_evaluate_rk12_ex(int64_t n, const double *eps_n, const double *eps_new,
+                                 const double *a_old, const uint8_t *phase,
+                                 const automat_params *params, double h, double atol,
+                                 double rtol, int32_t max_steps, double *sigma_out,
+                                 double *a_out, double *tangent_out, int32_t *steps_out,
+                                 uint64_t *nonconverged, void *stream);
 
 /* Single-precision evaluation (Section "Example", paragraph
  * "Parallelization": single precision works for this material law and pays

@@ -102,6 +102,10 @@ SIGNATURES = {
                                       _vp, _vp, _vp, _vp]),
     "automat_evaluate_rk12": (_i32, [_i64, _vp, _vp, _vp, _vp, _vp, _dbl, _dbl, _dbl, _i32, _vp,
                                       _vp, _vp, _vp, _vp]),
+    "automat_evaluate_rk23_ex": (_i32, [_i64, _vp, _vp, _vp, _vp, _vp, _dbl, _dbl, _dbl, _i32,
+                                         _vp, _vp, _vp, _vp, _vp, _vp]),
+    "automat_evaluate_rk12_ex": (_i32, [_i64, _vp, _vp, _vp, _vp, _vp, _dbl, _dbl, _dbl, _i32,
+                                         _vp, _vp, _vp, _vp, _vp, _vp]),
     "automat_evaluate_f32": (_i32, [_i64, _vp, _vp, _vp, _vp, _dbl, _dbl, _i32, _vp, _vp, _vp,
                                      _vp, _vp, _vp]),
     "automat_evaluate_conventional": (_i32, [_i64, _vp, _vp, _vp, _vp, _dbl, _dbl, _i32, _vp, _vp,

@@ -149,10 +149,13 @@ def evaluate_f32(eps, a_old, phase, phases, h=0.1, tol=1e-6, max_iter=50, *, tan
 
 
 def evaluate_rk23(eps_n, eps_new, a_old, phase, phases, h=0.1, atol=1e-6, rtol=1e-3,
-                  max_steps=100000, *, a_out=None, sigma_out=None, _entry="automat_evaluate_rk23"):
+                  max_steps=100000, *, tangent=False, a_out=None, sigma_out=None,
+                  tangent_out=None, _pair="rk23"):
     """Adaptive Bogacki-Shampine 3(2) evaluation over one load step with the
     strain moving linearly from eps_n to eps_new. Returns (sigma, a_new,
-    steps (n,) int32, failed-point count)."""
+    steps (n,) int32, failed-point count), with the consistent tangent
+    (36, n) after a_new if ``tangent`` (its entries then also enter the
+    step size control)."""
     eps_n = _field(eps_n, "eps_n", 6)
     n, dev = eps_n.shape[1], eps_n.device
     eps_new = _field(eps_new, "eps_new", 6, n, dev)
@@ -161,22 +164,35 @@ def evaluate_rk23(eps_n, eps_new, a_old, phase, phases, h=0.1, atol=1e-6, rtol=1
     params = make_params(phases)
     sigma = torch.empty_like(eps_n) if sigma_out is None else _field(sigma_out, "sigma_out", 6, n, dev)
     a_new = torch.empty_like(a_old) if a_out is None else _field(a_out, "a_out", 6, n, dev)
+    tan = None
+    if tangent:
+        tan = (torch.empty((36, n), dtype=torch.float64, device=dev) if tangent_out is None
+               else _field(tangent_out, "tangent_out", 36, n, dev))
     steps = torch.empty(n, dtype=torch.int32, device=dev)
     count = torch.zeros(1, dtype=torch.int64, device=dev)
+    lib = load()
     with torch.cuda.device(dev):
-        rc = getattr(load(), _entry)(n, _ptr(eps_n), _ptr(eps_new), _ptr(a_old), _ptr(phase),
-                                     ctypes.byref(params), float(h), float(atol), float(rtol),
-                                     int(max_steps), _ptr(sigma), _ptr(a_new), _ptr(steps),
-                                     _ptr(count), _stream(dev))
-    check(_entry, rc)
+        args = (n, _ptr(eps_n), _ptr(eps_new), _ptr(a_old), _ptr(phase), ctypes.byref(params),
+                float(h), float(atol), float(rtol), int(max_steps), _ptr(sigma), _ptr(a_new))
+        if tangent:
+            entry = f"automat_evaluate_{_pair}_ex"
+            rc = getattr(lib, entry)(*args, _ptr(tan), _ptr(steps), _ptr(count), _stream(dev))
+        else:
+            entry = f"automat_evaluate_{_pair}"
+            rc = getattr(lib, entry)(*args, _ptr(steps), _ptr(count), _stream(dev))
+    check(entry, rc)
+    if tangent:
+        return sigma, a_new, tan, steps, count
     return sigma, a_new, steps, count
 
 
 def evaluate_rk12(eps_n, eps_new, a_old, phase, phases, h=0.1, atol=1e-6, rtol=1e-3,
-                  max_steps=100000, *, a_out=None, sigma_out=None):
+                  max_steps=100000, *, tangent=False, a_out=None, sigma_out=None,
+                  tangent_out=None):
     """As evaluate_rk23 with the Heun-Euler 2(1) pair (ode12)."""
     return evaluate_rk23(eps_n, eps_new, a_old, phase, phases, h, atol, rtol, max_steps,
-                         a_out=a_out, sigma_out=sigma_out, _entry="automat_evaluate_rk12")
+                         tangent=tangent, a_out=a_out, sigma_out=sigma_out,
+                         tangent_out=tangent_out, _pair="rk12")
 
 
 def evaluate_backward(eps, a_old, a_new, phase, phases, h, grad_sigma=None, grad_a=None, *,

@@ -78,3 +78,61 @@ def test_empty_and_invalid_arguments(pair):
     e = torch.empty((6, 0), dtype=torch.float64, device="cuda")
     out = fn(e, e, e, torch.empty(0, dtype=torch.uint8, device="cuda"), ps.phases)
     assert out[0].shape == (6, 0)
+
+
+def _run_tan(e0, ps, h, pair, **kw):
+    from paper_2006_04391_amd import api
+    fn = getattr(api, "evaluate_" + pair)
+    sig, a, tan, steps, cnt = fn(T(e0), T(ps.eps), T(ps.a_old), T(ps.phase), ps.phases, h=h,
+                                 tangent=True, **kw)
+    torch.cuda.synchronize()
+    ref = getattr(oracle, "evaluate_" + pair)(e0, ps.eps, ps.a_old, ps.phase, ps.phases, h=h,
+                                              tangent=True, **kw)
+    return dict(sigma=N(sig), a_out=N(a), tangent=N(tan), steps=N(steps),
+                count=int(cnt.item())), ref
+
+
+@pytest.mark.parametrize("pair", PAIRS)
+@pytest.mark.parametrize("preset,n,seed", [("config", 1031, 11), ("paper", 517, 12)])
+def test_tangent_parity(preset, n, seed, pair):
+    """Consistent tangent of the adaptive schemes: the sensitivity system is
+    integrated with the same stages and steps, and its entries enter the
+    error measure, so the accepted steps, the state and the tangent all
+    match the oracle point by point."""
+    phases = inputs.config_phases() if preset == "config" else inputs.paper_phases()
+    e11, h = (2e-2, 10.0) if preset == "config" else (4e-3, 1.0)
+    ps = inputs.points_random(n, seed=seed, phases=phases, e11=e11, std=3e-4, a_std=1e-4)
+    e0 = 0.5 * ps.eps + 1e-4 * np.random.default_rng(seed).normal(size=ps.eps.shape)
+    g, ref = _run_tan(e0, ps, h=h, pair=pair)
+    assert ref["steps"].max() > 1
+    _check(g, ref)
+    ok = ref["steps"] >= 0
+    assert rel_per_point(g["tangent"][:, ok], ref["tangent"][:, ok]).max() <= TOL
+    # elastic points: the elastic stiffness exactly
+    el = ps.phase == 1
+    assert np.array_equal(g["tangent"][:, el], ref["tangent"][:, el])
+
+
+@pytest.mark.parametrize("pair", PAIRS)
+def test_tangent_invalid_points_and_step_limit(pair):
+    ps = inputs.points_random(300, seed=13, phases=inputs.paper_phases(), e11=6e-3, std=5e-4)
+    ps.eps[0, 7] = np.inf
+    ps.phase[11] = 9
+    e0 = np.zeros_like(ps.eps)
+    g, ref = _run_tan(e0, ps, h=1.0, pair=pair, max_steps=3)
+    assert (ref["steps"] < 0).sum() > 2 and g["steps"][7] == -1 and g["steps"][11] == -1
+    _check(g, ref)
+    assert np.all(np.isnan(g["tangent"][:, [7, 11]]))
+    ok = ref["steps"] >= 0
+    assert rel_per_point(g["tangent"][:, ok], ref["tangent"][:, ok]).max() <= TOL
+
+
+@pytest.mark.parametrize("pair,rtol", [("rk23", 1e-6), ("rk12", 1e-4)])
+def test_tangent_tight_tolerances_many_steps(pair, rtol):
+    ps = inputs.points_random(300, seed=14, phases=inputs.paper_phases(), e11=6e-3, std=5e-4)
+    e0 = np.zeros_like(ps.eps)
+    g, ref = _run_tan(e0, ps, h=1.0, pair=pair, atol=1e-3 * rtol, rtol=rtol)
+    assert ref["steps"].max() > 10
+    _check(g, ref)
+    ok = ref["steps"] >= 0
+    assert rel_per_point(g["tangent"][:, ok], ref["tangent"][:, ok]).max() <= TOL
