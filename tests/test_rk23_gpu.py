@@ -136,3 +136,28 @@ def test_tangent_tight_tolerances_many_steps(pair, rtol):
     _check(g, ref)
     ok = ref["steps"] >= 0
     assert rel_per_point(g["tangent"][:, ok], ref["tangent"][:, ok]).max() <= TOL
+
+
+def test_tangent_argument_errors():
+    from paper_2006_04391_amd import _lib, api
+    ps = inputs.points_random(64, seed=15, phases=inputs.config_phases())
+    e0, e1, a0, ph = T(np.zeros_like(ps.eps)), T(ps.eps), T(ps.a_old), T(ps.phase)
+    L = _lib.load()
+    params = _lib.make_params(ps.phases)
+    sig = torch.empty_like(e1)
+    an = torch.empty_like(e1)
+    steps = torch.empty(ps.n, dtype=torch.int32, device="cuda")
+    ptr = lambda t: t.data_ptr()
+    for bad_tan in (sig, an, e1):            # the tangent must not overlap another array
+        rc = L.automat_evaluate_rk23_ex(ps.n, ptr(e0), ptr(e1), ptr(a0), ptr(ph),
+                                        _lib.ctypes.byref(params), 0.1, 1e-6, 1e-3, 100,
+                                        ptr(sig), ptr(an), ptr(bad_tan), ptr(steps), None, None)
+        assert rc == _lib.EINVAL
+    # NULL tangent: the plain evaluation, same results as the plain entry point
+    s1, a1, st1, _ = api.evaluate_rk23(e0, e1, a0, ph, ps.phases)
+    rc = L.automat_evaluate_rk23_ex(ps.n, ptr(e0), ptr(e1), ptr(a0), ptr(ph),
+                                    _lib.ctypes.byref(params), 0.1, 1e-6, 1e-3, 100000,
+                                    ptr(sig), ptr(an), None, ptr(steps), None, None)
+    torch.cuda.synchronize()
+    assert rc == 0
+    assert torch.equal(sig, s1) and torch.equal(an, a1) and torch.equal(steps, st1)
