@@ -62,6 +62,9 @@ def lib():
                                            ctypes.c_void_p, ctypes.c_void_p]
         L.oracle_evaluate_rk12.restype = ctypes.c_int
         L.oracle_evaluate_rk12.argtypes = L.oracle_evaluate_rk23.argtypes
+        L.oracle_jvp.restype = ctypes.c_int
+        L.oracle_jvp.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_void_p, ctypes.c_int, dp,
+                                 ctypes.c_double, dp, dp, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -132,6 +135,29 @@ def backward(eps, a_old, a_new, phase, phases, h, grad_sigma=None, grad_a=None):
     if rc != 0:
         raise ValueError("oracle_backward: invalid arguments")
     return dict(grad_eps=geps, grad_a_old=gan, grad_params=gpar)
+
+
+def jvp(eps, a_new, phase, phases, h, d_eps=None, d_a_old=None, d_params=None):
+    """Jacobian-vector product of (sigma, a_{n+1}) at a converged step
+    (a_new from ``evaluate``) in the direction (d_eps, d_a_old, d_params);
+    d_params is (n_phases, 7) over GRAD_KEYS, one direction per phase.
+
+    Returns dict(d_sigma (6, n), d_a_new (6, n))."""
+    eps = _f64(eps)
+    n = eps.shape[1]
+    a_new = _f64(a_new, (6, n))
+    phase = np.ascontiguousarray(phase, dtype=np.uint8)
+    par = params_rows(phases)
+    de = None if d_eps is None else _f64(d_eps, (6, n))
+    da = None if d_a_old is None else _f64(d_a_old, (6, n))
+    dp = None if d_params is None else _f64(d_params, (par.shape[0], 7))
+    ds = np.empty((6, n))
+    dan = np.empty((6, n))
+    rc = lib().oracle_jvp(n, _dp(eps), _dp(a_new), phase.ctypes.data, par.shape[0], _dp(par),
+                          h, _dp(de), _dp(da), _dp(dp), _dp(ds), _dp(dan))
+    if rc != 0:
+        raise ValueError("oracle_jvp: invalid arguments")
+    return dict(d_sigma=ds, d_a_new=dan)
 
 
 def evaluate_rk12(eps_n, eps1, a_old, phase, phases, h=0.1, atol=1e-6, rtol=1e-3,

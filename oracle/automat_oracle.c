@@ -640,6 +640,135 @@ int oracle_backward(int64_t n, const double *eps, const double *a_old, const dou
     return 0;
 }
 
+/* ------------------------------------------------------------------------
+ * Forward (Jacobian-vector) product through the converged step, the same
+ * implicit-function argument as the tangent (Section "Single Implicit Euler
+ * Step", equation tangent_formula) with perturbed inputs instead of a
+ * perturbed strain only. At the converged a_{n+1} = a_n + Delta,
+ *   F(Delta; eps, a_n, p) = Delta - h f(A(eps, a_n + Delta; p); p) = 0,
+ *   A = C(p) (eps - a) - 2/3 H D a,   sigma = C(p) (eps - a_{n+1}).
+ * For a direction (d eps, d a_n, d p):
+ *   dA_x    = C d eps - K d a_n + (dA/dp) d p      (explicit part)
+ *   J d Delta = h Psi'' dA_x + h (df/dp) d p,      J = I + h Psi'' K
+ *   d a_{n+1} = d a_n + d Delta
+ *   d sigma   = C (d eps - d a_{n+1}) + (dC/dp) (eps - a_{n+1}) d p
+ * with dA/dE = C (eps - a) / E, dA/dnu = dC/dnu (eps - a), dA/dH = -2/3 D a,
+ * and the hand-derived partials of f in the viscous parameters:
+ *   df/dsigma_y = -eps0 n / sigma0 r^(n-1) grad q,  df/dsigma0 = -(n/sigma0) f,
+ *   df/deps0 = r^n grad q,  df/dn = log(r) f   (r = (q - sigma_y)^+ / sigma0;
+ * all zero where r = 0, one-sided in sigma_y at sigma_y = 0).
+ * ------------------------------------------------------------------------ */
+static void jvp_point(const phase_t *p, const double eps[6], const double anew[6], double h,
+                      const double de[6], const double dan[6], const double dp[7],
+                      double dsig[6], double danew[6])
+{
+    double C[6][6], K[6][6], Cn[6][6];
+    stiffness(p->E, p->nu, C);
+    stiffness_dnu(p->E, p->nu, Cn);
+    hessian_omega_aa(p, C, K);
+    double e[6], sig[6], dsnu[6];
+    for (int i = 0; i < 6; ++i) e[i] = eps[i] - anew[i];
+    matvec(C, e, sig);   /* = C (eps - a_{n+1}), also C (eps - a) in dA/dE */
+    matvec(Cn, e, dsnu); /* dC/dnu (eps - a_{n+1}) */
+
+    double A[6], f[6], P2[6][6];
+    memset(f, 0, sizeof f);
+    memset(P2, 0, sizeof P2);
+    memset(A, 0, sizeof A);
+    if (p->kind == 1) {
+        gen_stress(p, C, eps, anew, A);
+        force_potential(p, A, f, P2);
+    }
+    /* explicit change of A */
+    double Cde[6], Kda[6], dAx[6];
+    matvec(C, de, Cde);
+    matvec(K, dan, Kda);
+    for (int i = 0; i < 6; ++i)
+        dAx[i] = Cde[i] - Kda[i] + sig[i] / p->E * dp[0] + dsnu[i] * dp[1] -
+                 (2.0 / 3.0) * DIAG_D[i] * anew[i] * dp[2];
+    /* df/dp d p for the viscous parameters */
+    double dfp[6] = {0, 0, 0, 0, 0, 0};
+    if (p->kind == 1) {
+        double g[6];
+        deviator(A, g);
+        double J2 = 0.5 * (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) + A[3] * A[3] +
+                    A[4] * A[4] + A[5] * A[5];
+        double q = sqrt(3.0 * J2);
+        double x = q - p->sy;
+        if (x > 0.0) {
+            double r = x / p->s0;
+            double rn = pow(r, p->n);
+            for (int i = 0; i < 6; ++i) {
+                double gq = 1.5 / q * g[i];
+                double fi = p->e0 * rn * gq;
+                dfp[i] = -p->e0 * p->n / p->s0 * pow(r, p->n - 1.0) * gq * dp[3] -
+                         (p->n / p->s0) * fi * dp[4] + rn * gq * dp[5] + log(r) * fi * dp[6];
+            }
+        }
+    }
+    /* J d Delta = h Psi'' dA_x + h df/dp dp */
+    double J[6][6], dD[6], P2dA[6];
+    matvec(P2, dAx, P2dA);
+    for (int i = 0; i < 6; ++i) {
+        for (int j = 0; j < 6; ++j) {
+            double s = 0.0;
+            for (int l = 0; l < 6; ++l) s += P2[i][l] * K[l][j];
+            J[i][j] = (i == j ? 1.0 : 0.0) + h * s;
+        }
+        dD[i] = h * (P2dA[i] + dfp[i]);
+    }
+    if (gauss_solve(J, dD, 1, 1) != 0)
+        for (int i = 0; i < 6; ++i) dD[i] = NAN;
+    double da1[6], dee[6], Cdee[6];
+    for (int i = 0; i < 6; ++i) {
+        da1[i] = dan[i] + dD[i];
+        dee[i] = de[i] - da1[i];
+    }
+    matvec(C, dee, Cdee);
+    for (int i = 0; i < 6; ++i) {
+        dsig[i] = Cdee[i] + sig[i] / p->E * dp[0] + dsnu[i] * dp[1];
+        danew[i] = da1[i];
+    }
+}
+
+/* d_eps, d_a_old: [6][n] or NULL (zero); d_par: [n_phases][7] or NULL
+ * (zero), the parameter direction of each phase; d_sigma [6][n];
+ * d_a_new [6][n] or NULL. a_new is the converged state of oracle_evaluate.
+ * Unknown phases give NaN. Returns 0, or -1 on invalid arguments. */
+int oracle_jvp(int64_t n, const double *eps, const double *a_new, const uint8_t *phase,
+               int n_phases, const double *par, double h, const double *d_eps,
+               const double *d_a_old, const double *d_par, double *d_sigma, double *d_a_new)
+{
+    phase_t ph[256];
+    if (n < 0 || !eps || !a_new || !phase || !par || !d_sigma) return -1;
+    if (!(h > 0.0) || !isfinite(h)) return -1;
+    if (load_all(n_phases, par, ph) != 0) return -1;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double e[6], anw[6], de[6], dan[6], dp[7] = {0, 0, 0, 0, 0, 0, 0}, ds[6], da[6];
+        int pid = phase[i];
+        for (int c = 0; c < 6; ++c) {
+            e[c] = eps[c * n + i];
+            anw[c] = a_new[c * n + i];
+            de[c] = d_eps ? d_eps[c * n + i] : 0.0;
+            dan[c] = d_a_old ? d_a_old[c * n + i] : 0.0;
+        }
+        if (pid >= n_phases) {
+            for (int c = 0; c < 6; ++c) ds[c] = da[c] = NAN;
+        } else {
+            if (d_par)
+                for (int c = 0; c < ORACLE_NPAR_GRAD; ++c)
+                    dp[c] = d_par[pid * ORACLE_NPAR_GRAD + c];
+            jvp_point(&ph[pid], e, anw, h, de, dan, dp, ds, da);
+        }
+        for (int c = 0; c < 6; ++c) {
+            d_sigma[c * n + i] = ds[c];
+            if (d_a_new) d_a_new[c * n + i] = da[c];
+        }
+    }
+    return 0;
+}
+
 /* Convenience for tests: Psi'' and f at one generalized stress. */
 int oracle_force_potential(const double *row, const double A[6], double f[6], double P2[36],
                            double *psi)

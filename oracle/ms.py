@@ -105,6 +105,20 @@ def gamma_apply(tau_hat, shape, lam0, mu0):
     return np.where(ambiguous[None], comp, out)
 
 
+def gamma_matrix(shape, lam0, mu0):
+    """The operator of gamma_apply as one complex 6x6 matrix per frequency of
+    the half spectrum, (6, 6, nz, ny, nx//2 + 1): column d is the image of
+    the unit polarization e_d (the operator is linear and acts frequency by
+    frequency), so that an iteration applies it by one matrix product."""
+    nz, ny, nx = shape
+    G = np.empty((6, 6, nz, ny, nx // 2 + 1), dtype=complex)
+    for d in range(6):
+        unit = np.zeros((6, nz, ny, nx // 2 + 1), dtype=complex)
+        unit[d] = 1.0
+        G[:, d] = gamma_apply(unit, shape, lam0, mu0)
+    return G
+
+
 def voigt_stiffness(lam, mu):
     """Isotropic stiffness in engineering Voigt form (stress = C @ strain)."""
     C = np.zeros((6, 6))
@@ -189,6 +203,7 @@ def ms_step(eps, a, phase, phases, shape, E, E_prev, h, lam0=None, mu0=None, tol
         lam0, mu0 = reference_from_tangent(rt["tangent"])
     err = 0.0
     it = 0
+    G = gamma_matrix(shape, lam0, mu0)
     for it in range(1, max_iter + 1):
         r = evaluate(eps, a, phase, phases, h=h, tol=newton_tol, max_iter=newton_max_iter)
         tr = lam0 * (eps[0] + eps[1] + eps[2])
@@ -196,7 +211,7 @@ def ms_step(eps, a, phase, phases, shape, E, E_prev, h, lam0=None, mu0=None, tol
         tau[:3] -= tr + 2.0 * mu0 * eps[:3]
         tau[3:] -= mu0 * eps[3:]
         th = scipy.fft.rfftn(tau.reshape(6, nz, ny, nx), axes=(1, 2, 3))
-        eh = gamma_apply(th, shape, lam0, mu0)
+        eh = np.einsum("cd...,d...->c...", G, th)
         Ecur = _macro_strain(th[:, 0, 0, 0].real / n, E, S_bar, stress_mask, lam0, mu0)
         eh[:, 0, 0, 0] = Ecur * n
         new = scipy.fft.irfftn(eh, s=(nz, ny, nx), axes=(1, 2, 3)).reshape(6, n)
@@ -208,3 +223,83 @@ def ms_step(eps, a, phase, phases, shape, E, E_prev, h, lam0=None, mu0=None, tol
     r = evaluate(eps, a, phase, phases, h=h, tol=newton_tol, max_iter=newton_max_iter)
     return dict(eps=eps, a=r["a_out"], sigma=r["sigma"], sigma_mean=r["sigma"].mean(axis=1),
                 E=Ecur, iters=it, residual=err, lam0=lam0, mu0=mu0)
+
+
+def _gamma_field(x, G, shape):
+    """-Gamma0 * x for a real (6, n) field with the zero frequency removed."""
+    nz, ny, nx = shape
+    xh = scipy.fft.rfftn(x.reshape(6, nz, ny, nx), axes=(1, 2, 3))
+    yh = np.einsum("cd...,d...->c...", G, xh)
+    yh[:, 0, 0, 0] = 0.0
+    return scipy.fft.irfftn(yh, s=(nz, ny, nx), axes=(1, 2, 3)).reshape(6, -1)
+
+
+def linearized_step(eps, a_prev, a, phase, phases, shape, h, dE, d_a_prev=None, d_params=None,
+                    lam0=None, mu0=None, tol=1e-12, max_iter=2000):
+    """Forward derivative of one converged strain-controlled load step.
+
+    (eps, a) is the converged state that the step reached from a_prev under
+    the macroscopic strain E. The implicit function theorem (the paper's
+    Section "Single Implicit Euler Step", applied here to the fixed point of
+    the basic scheme instead of the Newton system) gives the change d eps of
+    the fixed point for a change (dE, d a_prev, d p) of the step's inputs as
+    the solution of the linearized Lippmann-Schwinger equation
+
+        d eps = dE - Gamma0 * (d sigma - C0 d eps),
+        d sigma = C_tan d eps + s,
+
+    with C_tan the consistent tangent field at the converged state and s the
+    stress change at fixed strain (from d a_prev and d p, the oracle's
+    Jacobian-vector product). Rearranged,
+        d eps + Gamma0 * ((C_tan - C0) d eps) = dE - Gamma0 * s,
+    a linear system for the 6n strain values, solved by GMRES (the converged
+    derivative does not depend on C0).
+
+    d_params: (n_phases, 7) over the oracle's GRAD_KEYS, or None.
+    Returns dict(d_eps, d_sigma (fields), d_sigma_mean (6,), d_a (the change
+    of a_{n+1}, for the next step's history), gmres_info)."""
+    from scipy.sparse.linalg import LinearOperator, gmres
+    from . import jvp
+    if lam0 is None or mu0 is None:
+        lam0, mu0 = reference_medium(phases)
+    nz, ny, nx = shape
+    n = nx * ny * nz
+    G = gamma_matrix(shape, lam0, mu0)
+    C0 = voigt_stiffness(lam0, mu0)
+    r = evaluate(eps, a_prev, phase, phases, h=h, tol=1e-14, max_iter=100, tangent=True)
+    Ct = r["tangent"].reshape(6, 6, n)
+    dCt = Ct - C0[:, :, None]
+    s = jvp(eps, a, phase, phases, h, d_a_old=d_a_prev, d_params=d_params)["d_sigma"]
+
+    def op(v):
+        x = v.reshape(6, n)
+        return (x - _gamma_field(np.einsum("cdn,dn->cn", dCt, x), G, shape)).reshape(-1)
+
+    dE = np.asarray(dE, dtype=np.float64)
+    b = (dE[:, None] + _gamma_field(s, G, shape)).reshape(-1)
+    L = LinearOperator((6 * n, 6 * n), matvec=op, dtype=np.float64)
+    x, info = gmres(L, b, x0=np.repeat(dE, n), rtol=tol, atol=0.0, restart=60,
+                    maxiter=max_iter)
+    de = x.reshape(6, n)
+    j = jvp(eps, a, phase, phases, h, d_eps=de, d_a_old=d_a_prev, d_params=d_params)
+    return dict(d_eps=de, d_sigma=j["d_sigma"], d_sigma_mean=j["d_sigma"].mean(axis=1),
+                d_a=j["d_a_new"], gmres_info=info)
+
+
+def linearized_history(history, phase, phases, shape, h, dE_steps, d_params=None, lam0=None,
+                       mu0=None, tol=1e-12):
+    """Forward derivative of the last step's mean stress over a load history.
+
+    history: the converged steps [(eps_1, a_0, a_1), ..., (eps_K, a_{K-1}, a_K)]
+    of a strain-controlled run from a_0; dE_steps: (K, 6) changes of the
+    macroscopic strains; d_params as in linearized_step. The change of a_k
+    carries into step k + 1. Returns d mean(sigma_K) (6,)."""
+    d_a = None
+    out = None
+    for (eps, a_prev, a), dE in zip(history, dE_steps):
+        out = linearized_step(eps, a_prev, a, phase, phases, shape, h, dE, d_a_prev=d_a,
+                              d_params=d_params, lam0=lam0, mu0=mu0, tol=tol)
+        if out["gmres_info"] != 0:
+            raise RuntimeError(f"GMRES did not converge ({out['gmres_info']})")
+        d_a = out["d_a"]
+    return out["d_sigma_mean"]

@@ -321,3 +321,78 @@ def test_reference_update_same_solution_fewer_iterations():
     assert np.abs(u["sigma"] - f["sigma"]).max() <= 1e-7 * scale
     np.testing.assert_allclose(u["E"], f["E"], rtol=1e-7)
     assert abs(f["sigma_mean"][1:]).max() <= 1e-8 * abs(f["sigma_mean"][0])
+
+
+# ---------------------------------------------------------------------------
+# linearized scheme (forward derivative of converged load steps)
+# ---------------------------------------------------------------------------
+
+def test_linearized_step_gives_the_laminate_stiffness():
+    """On an elastic laminate the linearized Lippmann-Schwinger solve for a
+    unit macroscopic strain returns the column of the exact laminate
+    stiffness (tangential strains and normal tractions uniform)."""
+    nz, ny, nx = 4, 4, 16
+    ph = [ELASTIC(2500.0, 0.35), ELASTIC(72000.0, 0.22)]
+    layer = (np.arange(nx) >= 11).astype(np.uint8)
+    phase = np.broadcast_to(layer[None, None, :], (nz, ny, nx)).reshape(-1).copy()
+    z = np.zeros((6, phase.size))
+    C = np.array([laminate_sigma(ph, [11 / 16, 5 / 16], np.eye(6)[c]) for c in range(6)]).T
+    for c in range(6):
+        r = oms.linearized_step(z, z, z, phase, ph, (nz, ny, nx), 0.1, np.eye(6)[c])
+        assert r["gmres_info"] == 0
+        np.testing.assert_allclose(r["d_sigma_mean"], C[:, c], rtol=1e-10,
+                                   atol=1e-10 * np.abs(C).max())
+
+
+def _converged_history(shape, phase, ph, loads, h, tol=1e-13):
+    n = phase.size
+    eps, a, prev = np.zeros((6, n)), np.zeros((6, n)), np.zeros(6)
+    hist = []
+    for E in loads:
+        r = oms.ms_step(eps, a, phase, ph, shape, E, prev, h, tol=tol, max_iter=5000,
+                        newton_tol=1e-14)
+        assert r["residual"] <= tol
+        hist.append((r["eps"], a, r["a"]))
+        eps, a, prev = r["eps"], r["a"], np.asarray(E, dtype=float)
+    return hist, r["sigma_mean"]
+
+
+def test_linearized_history_against_central_differences_of_the_scheme():
+    """Two flowing load steps on a random two-phase grid: the forward
+    derivative of <sigma_2> in E_2, in E_1 (through the history of a) and in
+    the matrix parameters E, sigma0 and n, against central differences of
+    the scheme converged to 1e-13 (relative step 1e-5: the stopping rules
+    make the discrete map piecewise smooth with jumps near 1e-13; truncation
+    and those jumps stay near 1e-10 relative, gate 1e-8)."""
+    shape = (4, 6, 8)
+    nz, ny, nx = shape
+    rng = np.random.default_rng(11)
+    phase = (rng.random(nz * ny * nx) < 0.25).astype(np.uint8)
+    ph = inputs.paper_phases()
+    h = 1.0
+    loads = [[2e-3 * k, -5e-4 * k, 0, 0, 3e-4 * k, 0] for k in (1, 2)]
+    hist, _ = _converged_history(shape, phase, ph, loads, h)
+
+    def mean_after(loads_, ph_):
+        return _converged_history(shape, phase, ph_, loads_, h)[1]
+
+    step = 1e-5 * np.linalg.norm(loads[-1])
+    for k, c in ((1, 0), (1, 5), (0, 0)):
+        dE = np.zeros((2, 6))
+        dE[k, c] = 1.0
+        lin = oms.linearized_history(hist, phase, ph, shape, h, dE)
+        lp = [list(x) for x in loads]
+        lm = [list(x) for x in loads]
+        lp[k][c] += step
+        lm[k][c] -= step
+        fd = (mean_after(lp, ph) - mean_after(lm, ph)) / (2 * step)
+        assert np.abs(lin - fd).max() <= 1e-8 * np.abs(fd).max(), (k, c, lin, fd)
+    for key in ("E", "sigma0", "n"):
+        p0 = ph[0][key]
+        d = 1e-5 * abs(p0)
+        dp = np.zeros((2, 7))
+        dp[0, oracle.GRAD_KEYS.index(key)] = 1.0
+        lin = oms.linearized_history(hist, phase, ph, shape, h, np.zeros((2, 6)), d_params=dp)
+        fd = (mean_after(loads, [dict(ph[0], **{key: p0 + d}), ph[1]])
+              - mean_after(loads, [dict(ph[0], **{key: p0 - d}), ph[1]])) / (2 * d)
+        assert np.abs(lin - fd).max() <= 1e-8 * np.abs(fd).max(), (key, lin, fd)

@@ -433,6 +433,88 @@ def test_backward_adjoint_identity_and_elastic_E():
 
 
 # ---------------------------------------------------------------------------
+# forward (Jacobian-vector) product
+# ---------------------------------------------------------------------------
+
+def _outputs(eps, a_old, phases, h=0.1):
+    r = oracle.evaluate(eps, a_old, np.zeros(eps.shape[1], np.uint8), phases, h=h, tol=1e-15,
+                        max_iter=100)
+    return r["sigma"], r["a_out"]
+
+
+@pytest.mark.parametrize("preset", ["config", "paper", "linear", "elastic"])
+def test_jvp_central_differences(preset):
+    """d sigma and d a_{n+1} in a random direction of (eps, a_n) and along
+    each parameter against central differences of the forward oracle."""
+    rng = np.random.default_rng(43)
+    if preset == "config":
+        ph = _phase_row(eps0=0.1, H=300.0, sigma_y=2.0)
+        e11, std = 2e-2, 3e-3
+    elif preset == "paper":
+        ph = inputs.paper_phases()[0]
+        e11, std = 1e-2, 2e-3
+    elif preset == "linear":
+        ph = _phase_row(n=1.0, eps0=0.1)
+        e11, std = 2e-2, 3e-3
+    else:
+        ph = inputs.config_phases()[1]
+        e11, std = 2e-3, 1e-4
+    n = 3
+    eps = inputs.uniaxial_strain(n, e11, std, rng)
+    a_old = inputs.deviatoric_draw(n, 1e-3, rng)
+    r = oracle.evaluate(eps, a_old, np.zeros(n, np.uint8), [ph], tol=1e-15, max_iter=100)
+    de = rng.normal(size=(6, n)) * np.abs(eps).max()
+    da = rng.normal(size=(6, n)) * 1e-3
+    j = oracle.jvp(eps, r["a_out"], np.zeros(n, np.uint8), [ph], 0.1, d_eps=de, d_a_old=da)
+    st = 1e-6
+    sp, ap = _outputs(eps + st * de, a_old + st * da, [ph])
+    sm, am = _outputs(eps - st * de, a_old - st * da, [ph])
+    for got, fd in ((j["d_sigma"], (sp - sm) / (2 * st)), (j["d_a_new"], (ap - am) / (2 * st))):
+        assert np.abs(got - fd).max() <= 1e-6 * max(np.abs(fd).max(), 1e-300), (got, fd)
+    keys = oracle.GRAD_KEYS if ph["kind"] == 1 else ("E", "nu")
+    for k in keys:
+        kk = oracle.GRAD_KEYS.index(k)
+        base = ph[k]
+        stp = 1e-6 * abs(base) if base != 0 else 1e-6
+        dp = np.zeros((1, 7))
+        dp[0, kk] = 1.0
+        j = oracle.jvp(eps, r["a_out"], np.zeros(n, np.uint8), [ph], 0.1, d_params=dp)
+        sp, ap = _outputs(eps, a_old, [dict(ph, **{k: base + stp})])
+        lower = {"n": 1.0, "nu": -1.0}.get(k, 0.0)        # smallest valid value
+        if base - stp >= lower:
+            sm, am = _outputs(eps, a_old, [dict(ph, **{k: base - stp})])
+            den = 2 * stp
+        else:                                  # one-sided at sigma_y = 0 or n = 1
+            sm, am = _outputs(eps, a_old, [ph])
+            den = stp
+        for got, fd in ((j["d_sigma"], (sp - sm) / den), (j["d_a_new"], (ap - am) / den)):
+            scale = max(np.abs(fd).max(), np.abs(got).max(), 1e-300)
+            assert np.abs(got - fd).max() <= 2e-5 * scale, (k, got, fd)
+
+
+def test_jvp_adjoint_identity_with_vjp():
+    """<g_s, d sigma> + <g_a, d a_{n+1}> = <grad eps, d eps> + <grad a_n, d a_n>
+    + sum over phases of grad p . d p: the forward and reverse products are
+    transposes of one linear map (two separate hand derivations)."""
+    rng = np.random.default_rng(47)
+    ph = [dict(inputs.paper_phases()[0]), inputs.paper_phases()[1],
+          _phase_row(n=1.0, eps0=0.1)]
+    n = 300
+    ps = inputs.points_random(n, seed=49, phases=ph[:2], e11=1e-2, std=2e-3, a_std=1e-3)
+    phase = rng.integers(0, 3, n).astype(np.uint8)
+    r = oracle.evaluate(ps.eps, ps.a_old, phase, ph)
+    gs, ga = rng.normal(size=(6, n)), rng.normal(size=(6, n)) * 1e4
+    de, da = rng.normal(size=(6, n)) * 1e-3, rng.normal(size=(6, n)) * 1e-4
+    dp = rng.normal(size=(3, 7)) * np.array([[p.get(k, 1.0) or 1.0 for k in oracle.GRAD_KEYS]
+                                               for p in ph]) * 1e-2
+    j = oracle.jvp(ps.eps, r["a_out"], phase, ph, 0.1, d_eps=de, d_a_old=da, d_params=dp)
+    b = oracle.backward(ps.eps, ps.a_old, r["a_out"], phase, ph, 0.1, gs, ga)
+    lhs = np.sum(gs * j["d_sigma"]) + np.sum(ga * j["d_a_new"])
+    terms = [np.sum(b["grad_eps"] * de), np.sum(b["grad_a_old"] * da), np.sum(b["grad_params"] * dp)]
+    assert abs(lhs - sum(terms)) <= 1e-11 * max(abs(t) for t in terms + [lhs])
+
+
+# ---------------------------------------------------------------------------
 # failure handling
 # ---------------------------------------------------------------------------
 
