@@ -161,3 +161,44 @@ def test_tangent_argument_errors():
     torch.cuda.synchronize()
     assert rc == 0
     assert torch.equal(sig, s1) and torch.equal(an, a1) and torch.equal(steps, st1)
+
+
+@pytest.mark.parametrize("pair", PAIRS)
+def test_full_size_ramp_parity(pair):
+    """The benchmark's adaptive leg: the 256^3 fibre batch with the strain
+    ramping from 0.8 eps to eps over h = 0.1 s, in its launch configuration
+    (a grid of four blocks per compute unit, so every wave strides over
+    about 64 tiles): accepted steps, stress and internal variables of every
+    point against the oracle."""
+    from tests.test_parity_gpu import points_c1
+    ps = points_c1()
+    e0 = 0.8 * ps.eps
+    g, ref = _run(e0, ps, h=ps.h, pair=pair)
+    _check(g, ref)
+    assert g["count"] == 0
+
+
+@pytest.mark.parametrize("pair", PAIRS)
+def test_strided_flowing_many_steps(pair):
+    """More points than the grid holds resident threads (2^19 + 77), strongly
+    flowing so that lanes of one wave take different numbers of steps
+    across the stride loop."""
+    n = (1 << 19) + 77
+    ps = inputs.points_random(n, seed=16, phases=inputs.config_phases(), e11=2e-2, std=3e-4,
+                              a_std=1e-4)
+    e0 = 0.5 * ps.eps + 1e-4 * np.random.default_rng(16).normal(size=ps.eps.shape)
+    g, ref = _run(e0, ps, h=10.0, pair=pair)
+    assert ref["steps"].max() > 2
+    _check(g, ref)
+
+
+@pytest.mark.parametrize("pair", PAIRS)
+def test_tangent_full_batch_128(pair):
+    """The tangent kernels on the 128^3 fibre batch (2^21 points, one wave
+    per 64 points) with the benchmark's ramp: accepted steps, state and all
+    tangent entries of every point against the oracle."""
+    ps = inputs.points_c1(N=128)
+    e0 = 0.8 * ps.eps
+    g, ref = _run_tan(e0, ps, h=ps.h, pair=pair)
+    _check(g, ref)
+    assert rel_per_point(g["tangent"], ref["tangent"]).max() <= TOL

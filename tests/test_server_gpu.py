@@ -161,3 +161,35 @@ def test_invalid_requests():
     (res,) = _drain(srv, [rid])
     assert res["status"] == 0 and "sigma" not in res
     srv.close()
+
+
+def test_mix_larger_than_the_resident_grid():
+    """More tiles in one batch than the batch kernel's resident grid holds
+    blocks (four 48^3 requests: 1728 tiles of 256 points against at most a
+    few blocks per compute unit), so blocks move from tile to tile and from
+    one request to the next inside a launch (drain the wave queues, reload
+    the descriptor and phase table): every request against the oracle and
+    against the same request served alone."""
+    reqs = [_request(s, k, 60 + j, steps) for j, (s, k, steps) in
+            enumerate([(48, "fibre", 3), (48, "sphere", 2), (48, "fibre", 1), (48, "sphere", 4),
+                       (11, "fibre", 2)])]
+    tiles = sum((q["phase"].size + 255) // 256 for q in reqs)
+    assert tiles > 4 * torch.cuda.get_device_properties(0).multi_processor_count
+    srv = _server()
+    ids = [srv.submit(**q, want_fields=True) for q in reqs]
+    mixed = _drain(srv, ids, timeout=120.0)
+    st = srv.stats()
+    srv.close()
+    assert st["launches"] < sum(q["steps"] for q in reqs)
+    seq = _server(sequential=True)
+    ids = [seq.submit(**q, want_fields=True) for q in reqs]
+    alone = _drain(seq, ids, timeout=120.0)
+    seq.close()
+    for q, m, s in zip(reqs, mixed, alone):
+        assert m["status"] == s["status"] == 0
+        assert rel_per_point(m["sigma"], s["sigma"]).max() <= 1e-12
+        assert rel_per_point(m["a"], s["a"]).max() <= 1e-12
+        sig, a, fails = _oracle_final(q)
+        assert m["nonconverged"] == fails == 0
+        _check(m, sig, a)
+        assert np.abs(a).max() > 0
