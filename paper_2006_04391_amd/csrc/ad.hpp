@@ -550,20 +550,10 @@ struct Pow : Expr<Pow<U, P>> {
         u.prep();
         p.prep();
         const double uv = u.v(), pv = p.v();
-        // a constant integer exponent >= 1: the partials in u by products
-        // (the exponent carries no derivative, so log u is not needed).
         // Every branch fills locals and the members are assigned once, so
         // the node stays in registers.
-        const bool by_products =
-            std::is_same_v<P, Cst> && uv > 0.0 && pv >= 1.0 && fm::small_int_exponent(pv);
         double Y = 0.0, Yu = 0.0, Yp = 0.0, Yuu = 0.0, Yup = 0.0, Ypp = 0.0;
-        if (by_products) {
-            const double w2 = pv == 1.0 ? 0.0 : fm::pow_int(uv, (int)pv - 2);  // u^(p-2)
-            const double w1 = pv == 1.0 ? 1.0 : w2 * uv;                       // u^(p-1)
-            Y = w1 * uv;
-            Yu = pv * w1;
-            Yuu = (pv - 1.0) * pv * w2;
-        } else if (uv > 0.0) {
+        if (uv > 0.0) {
             const double lu = fm::log(uv);
             const double iu = fm::rcp(uv);
             Y = fm::exp(pv * lu);

@@ -22,7 +22,7 @@
 //    Taylor series to r^13 (truncation < 5e-18), scaled by 2^k.
 // Domain: rcp, rsqrt for finite x > 0; log for finite x > 0 (subnormal x
 // handled by a pre-scale); exp for any x (underflow to 0, overflow to inf);
-// pow_pos for finite x > 0 (integer exponents 0..8 by products).
+// pow_pos for finite x > 0.
 // Host and device run the same refinement and polynomial code; only the
 // initial estimate of rcp / rsqrt differs (hardware on the device, a
 // single-precision estimate on the host), which the refinement removes to
@@ -165,25 +165,10 @@ AD_FN double exp(double x) {
     return ::ldexp(p, (int)kd);
 }
 
-// x^e for finite x > 0. An integer exponent in [0, 8] (the power laws of
-// common viscoplastic models have small integer exponents) is taken by at
-// most three products, which is also shorter as a dependency chain than the
-// logarithm and exponential; any other exponent as exp(e log x).
-AD_FN bool small_int_exponent(double e) { return e >= 0.0 && e <= 8.0 && e == ::rint(e); }
-
-AD_FN double pow_int(double x, int k) {  // k in [0, 8]
-    const double x2 = x * x, x4 = x2 * x2;
-    if (k == 8) return x4 * x4;
-    double r = (k & 1) ? x : 1.0;
-    if (k & 2) r *= x2;
-    if (k & 4) r *= x4;
-    return r;
-}
-
-AD_FN double pow_pos(double x, double e) {
-    if (small_int_exponent(e)) return pow_int(x, (int)e);
-    return exp(e * log(x));
-}
+// x^e for finite x > 0 as exp(e log x), for every exponent: the power-law
+// exponent is a material parameter that is varied and differentiated, so no
+// exponent takes a separate path.
+AD_FN double pow_pos(double x, double e) { return exp(e * log(x)); }
 
 }  // namespace fm
 }  // namespace automat
