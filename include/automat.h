@@ -389,7 +389,8 @@ int32_t automat_server_destroy(automat_server *server);
  * the trial deviator and q solves
  *   q + (3 mu + H) h eps0 ((q - sigma_y)^+ / sigma0)^n = q_tr
  * by Newton from q_tr (monotone), stopped when a step is <= tol q.
- * Arguments and layout as automat_evaluate_ex (no tangent, no flags);
+ * Arguments and layout as automat_evaluate_ex (no tangent, no flags; the
+ * tangent comes with automat_evaluate_conventional_ex);
  * iters_out: Newton steps (0 without flow), -1 for invalid input or no
  * convergence within max_iter. */
 int32_t automat_evaluate_conventional(int64_t n, const double *eps_new, const double *a_old,
@@ -397,6 +398,27 @@ int32_t automat_evaluate_conventional(int64_t n, const double *eps_new, const do
                                       double h, double tol, int32_t max_iter, double *sigma_out,
                                       double *a_out, int32_t *iters_out, uint64_t *nonconverged,
                                       void *stream);
+
+/* The conventional strategy with its consistent tangent (Section "Single
+ * Implicit Euler Step", the tangent of the converged step; Table
+ * "implicit_euler_timings" compares the strategies with and without it),
+ * derived by hand from the same scalar reduction:
+ *   C_tan = kappa I (x) I + 2 mu theta I_dev + 2 mu (beta - theta) N (x) N,
+ * N the unit trial deviator, theta = 1 - 3 mu dp / q_tr,
+ * beta = 1 - 3 mu c / (1 + c (3 mu + H)), dp = h eps0 x^n,
+ * c = h eps0 n x^(n-1) / sigma0, x = (q - sigma_y) / sigma0 at the converged
+ * q; the elastic stiffness without flow.
+ * tangent_out: device [36][n] (row-major 6x6 per point, engineering-shear
+ * Voigt, d sigma / d eps at fixed a_n), or NULL (then exactly
+ * automat_evaluate_conventional); it must not overlap another argument
+ * array (AUTOMAT_EINVAL for the same base pointer). NaN for invalid points.
+ * Other arguments and errors as automat_evaluate_conventional. */
+int32_t automat_evaluate_conventional_ex(int64_t n, const double *eps_new, const double *a_old,
+                                         const uint8_t *phase, const automat_params *params,
+                                         double h, double tol, int32_t max_iter,
+                                         double *sigma_out, double *a_out, double *tangent_out,
+                                         int32_t *iters_out, uint64_t *nonconverged,
+                                         void *stream);
 
 /* ------------------------------------------------------------------------
  * Adaptive explicit Runge-Kutta evaluation (Section "Rosenbrock and

@@ -110,6 +110,8 @@ SIGNATURES = {
                                      _vp, _vp, _vp]),
     "automat_evaluate_conventional": (_i32, [_i64, _vp, _vp, _vp, _vp, _dbl, _dbl, _i32, _vp, _vp,
                                               _vp, _vp, _vp]),
+    "automat_evaluate_conventional_ex": (_i32, [_i64, _vp, _vp, _vp, _vp, _dbl, _dbl, _i32, _vp,
+                                                 _vp, _vp, _vp, _vp, _vp]),
     "automat_strerror": (ctypes.c_char_p, [_i32]),
     "automat_version": (ctypes.c_char_p, []),
 }

@@ -90,9 +90,10 @@ def evaluate(eps, a_old, phase, phases, h=0.1, tol=1e-12, max_iter=50, *, tangen
 
 
 def evaluate_conventional(eps, a_old, phase, phases, h=0.1, tol=1e-12, max_iter=50, *,
-                          a_out=None, sigma_out=None):
+                          tangent=False, a_out=None, sigma_out=None, tangent_out=None):
     """Hand-reduced radial-return evaluation (the paper's conventional
-    strategy). Returns (sigma, a_new, iters (n,) int32, failed-point count)."""
+    strategy). Returns (sigma, a_new[, C (36, n)], iters (n,) int32,
+    failed-point count)."""
     eps = _field(eps, "eps", 6)
     n, dev = eps.shape[1], eps.device
     a_old = _field(a_old, "a_old", 6, n, dev)
@@ -100,14 +101,21 @@ def evaluate_conventional(eps, a_old, phase, phases, h=0.1, tol=1e-12, max_iter=
     params = make_params(phases)
     sigma = torch.empty_like(eps) if sigma_out is None else _field(sigma_out, "sigma_out", 6, n, dev)
     a_new = torch.empty_like(a_old) if a_out is None else _field(a_out, "a_out", 6, n, dev)
+    C = None
+    if tangent:
+        C = (torch.empty((36, n), dtype=torch.float64, device=dev) if tangent_out is None
+             else _field(tangent_out, "tangent_out", 36, n, dev))
     iters = torch.empty(n, dtype=torch.int32, device=dev)
     count = torch.zeros(1, dtype=torch.int64, device=dev)
     with torch.cuda.device(dev):
-        rc = load().automat_evaluate_conventional(n, _ptr(eps), _ptr(a_old), _ptr(phase),
-                                                  ctypes.byref(params), float(h), float(tol),
-                                                  int(max_iter), _ptr(sigma), _ptr(a_new),
-                                                  _ptr(iters), _ptr(count), _stream(dev))
-    check("automat_evaluate_conventional", rc)
+        rc = load().automat_evaluate_conventional_ex(n, _ptr(eps), _ptr(a_old), _ptr(phase),
+                                                     ctypes.byref(params), float(h), float(tol),
+                                                     int(max_iter), _ptr(sigma), _ptr(a_new),
+                                                     _ptr(C), _ptr(iters), _ptr(count),
+                                                     _stream(dev))
+    check("automat_evaluate_conventional_ex", rc)
+    if tangent:
+        return sigma, a_new, C, iters, count
     return sigma, a_new, iters, count
 
 
