@@ -86,32 +86,102 @@ def time_calls(fn, steps, warmup, stream):
     return total_ms, each, wall
 
 
-def cpu_baseline(ps, budget_s=30.0):
-    """Time the oracle on growing prefixes of the batch until one takes at
-    least budget_s/3 seconds; if the whole batch is quicker than that, time
-    repeated passes over it until budget_s/3 seconds have accumulated."""
+def latency_c0(dev, calls=200):
+    """The 4096-point parity set (70 % viscoplastic matrix, 30 % elastic
+    inclusion, h = 0.1 s): latency of one evaluation call, inputs resident
+    on the device. end_to_end: the Python call through the binding plus a
+    stream synchronization, host clock; kernel: events around the launch."""
+    import torch
+    from paper_2006_04391_amd import api, inputs
+    ps = inputs.points_c0()
+    eps = torch.from_numpy(ps.eps).to(dev)
+    a_old = torch.from_numpy(ps.a_old).to(dev)
+    phase = torch.from_numpy(ps.phase).to(dev)
+    sigma = torch.empty_like(eps)
+    a_new = torch.empty_like(a_old)
+    tan = torch.empty((36, ps.n), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    out = {"workload": "4096 points (2867 viscoplastic matrix, 1229 elastic inclusion), "
+                       "h = 0.1 s, tol 1e-12, inputs resident on the device"}
+    for key, tangent in (("no_tangent", False), ("tangent", True)):
+        def call():
+            api.evaluate(eps, a_old, phase, ps.phases, ps.h, ps.tol, ps.max_iter,
+                         sigma_out=sigma, a_out=a_new, tangent=tangent,
+                         tangent_out=tan if tangent else None)
+        for _ in range(20):
+            call()
+        torch.cuda.synchronize()
+        host = []
+        for _ in range(calls):
+            t0 = time.perf_counter()
+            call()
+            torch.cuda.synchronize()
+            host.append(time.perf_counter() - t0)
+        _, each, _ = time_calls(call, calls, 5, stream)
+        out[key] = {"end_to_end_us_median": float(np.median(host)) * 1e6,
+                    "end_to_end_us_p99": float(np.percentile(host, 99)) * 1e6,
+                    "kernel_us_median": float(np.median(each)) * 1e3}
+        log(f"[bench] 4096 points ({key}): end-to-end {np.median(host) * 1e6:.1f} us, "
+            f"kernel {np.median(each) * 1e3:.1f} us")
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(ps, target_s=3.0):
+    """The oracle (plain C, gcc -O3, no fast-math, OpenMP static schedule, one
+    point per iteration) on a prefix of the 256^3 batch: the compute call
+    alone, median of three runs, on all host threads and on one. The prefix
+    grows until one all-thread run takes about target_s; the one-thread
+    sample is that prefix divided by the thread count."""
     import oracle
-    n_total = ps.n
-    m = 1 << 16
-    while True:
-        m = min(m, n_total)
-        eps = np.ascontiguousarray(ps.eps[:, :m])
-        a_old = np.ascontiguousarray(ps.a_old[:, :m])
-        phase = np.ascontiguousarray(ps.phase[:m])
-        reps, dt = 0, 0.0
-        while True:
+    threads = oracle.num_threads()
+
+    def sample(m):
+        return (np.ascontiguousarray(ps.eps[:, :m]), np.ascontiguousarray(ps.a_old[:, :m]),
+                np.ascontiguousarray(ps.phase[:m]))
+
+    def median3(m):
+        eps, a_old, phase = sample(m)
+        ts = []
+        for _ in range(3):
             t0 = time.perf_counter()
             oracle.evaluate(eps, a_old, phase, ps.phases, h=ps.h, tol=ps.tol, max_iter=ps.max_iter)
-            dt += time.perf_counter() - t0
-            reps += 1
-            if m < n_total or dt >= budget_s / 3:
-                break
-        if dt >= budget_s / 3 or m == n_total:
-            return dict(value=m * reps / dt, unit="updates/s", cores=oracle.num_threads(),
-                        kind="oracle",
-                        sample=f"first {m} of {n_total} points of the 256^3 fibre batch, "
-                               f"no tangent, {reps} pass(es), {dt:.2f} s")
-        m *= 4
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)), ts
+
+    m = 1 << 18
+    while True:
+        m = min(m, ps.n)
+        t, ts = median3(m)
+        if t >= target_s or m == ps.n:
+            break
+        m = min(ps.n, int(m * max(2.0, 1.2 * target_s / max(t, 1e-3))))
+    m1 = max(1 << 14, m // threads)
+    oracle.set_num_threads(1)
+    try:
+        t1, ts1 = median3(m1)
+    finally:
+        oracle.set_num_threads(threads)
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count()
+    return dict(value=m / t, unit="updates/s", cores=threads, kind="oracle",
+                cpu_model=cpu_model(), nproc=nproc, one_core_value=m1 / t1,
+                sample=f"first {m} of {ps.n} points of the 256^3 fibre batch (one core: first "
+                       f"{m1}), no tangent, compute call only, median of 3 runs "
+                       f"({', '.join(f'{x:.2f}' for x in ts)} s on {threads} threads; "
+                       f"{', '.join(f'{x:.2f}' for x in ts1)} s on 1 thread)")
 
 
 def ms_bench(steps, N=128, h=0.1, tol=1e-6):
@@ -261,9 +331,10 @@ def main():
     total_ms, each, wall = time_calls(step, args.steps, args.warmup, stream)
     ms = total_ms / args.steps
     value = n / (ms * 1e-3)
-    avg_launch_ms = float(np.mean(each))
-    achieved = BYTES_PER_POINT * n / (avg_launch_ms * 1e-3) / 1e9
-    log(f"[bench] forward: {ms:.3f} ms/step, {value:.3e} updates/s, {achieved:.0f} GB/s")
+    # the roofline figures use the same time as ms_per_step
+    achieved = BYTES_PER_POINT * n / (ms * 1e-3) / 1e9
+    log(f"[bench] forward: {ms:.3f} ms/step, {value:.3e} updates/s, {achieved:.0f} GB/s "
+        f"(per-launch events: median {np.median(each):.3f} ms)")
 
     # iteration profile of the batch (for the FLOP side of the roofline)
     _, _, iters, cnt = api.evaluate(eps, a_old, phase, ps.phases, ps.h, ps.tol, ps.max_iter,
@@ -303,12 +374,30 @@ def main():
             "bytes_per_point": BYTES_PER_POINT,
         },
     }
+    out["launch_ms_median"] = float(np.median(each))
     fpp = MEASURED_FP64_FLOP_PER_POINT.get(kernel_source_hash())
     if fpp is not None:
-        tf = fpp * n / (avg_launch_ms * 1e-3) / 1e12
+        tf = fpp * n / (ms * 1e-3) / 1e12
         out["roofline"]["fp64"] = {"executed_flop_per_point": fpp, "achieved": tf,
                                    "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                                    "frac": tf / FP64_PEAK_TFLOPS}
+
+    # the same batch with a non-integer power-law exponent (n = 5.1): every
+    # exponent takes the same exp/log path, so this costs what n = 5 costs
+    ph51 = [dict(ps.phases[0], n=5.1), ps.phases[1]]
+
+    def step51():
+        api.evaluate(eps, a_old, phase, ph51, ps.h, ps.tol, ps.max_iter,
+                     sigma_out=sigma, a_out=a_new)
+    t51, _, _ = time_calls(step51, args.steps, args.warmup, stream)
+    ms51 = t51 / args.steps
+    a51 = BYTES_PER_POINT * n / (ms51 * 1e-3) / 1e9
+    out["exponent_5_1"] = {"workload": "same 256^3 batch, matrix exponent n = 5.1",
+                           "ms_per_step": ms51, "value": n / (ms51 * 1e-3), "unit": "updates/s",
+                           "roofline_frac": a51 / HBM_PEAK_GBS}
+    log(f"[bench] n = 5.1: {ms51:.3f} ms/step, {a51 / HBM_PEAK_GBS:.3f} of the HBM roofline")
+
+    out["latency_4096"] = latency_c0(dev)
 
     if not args.no_tangent:
         # the tangent field (36 doubles per point, 4.8 GB) is allocated once,

@@ -29,9 +29,10 @@ GRAD_KEYS = ("E", "nu", "H", "sigma_y", "sigma0", "eps0", "n")
 
 
 def build() -> str:
-    """Compile the oracle with gcc: -O2, no fast-math, OpenMP."""
+    """Compile the oracle with gcc: -O3, no fast-math, no contraction of
+    products and sums into fused operations, OpenMP."""
     tmp = _SO + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+    cmd = ["gcc", "-O3", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
            "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, _SO)
@@ -55,6 +56,8 @@ def lib():
         L.oracle_force_potential.restype = ctypes.c_int
         L.oracle_force_potential.argtypes = [dp, dp, dp, dp, dp]
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_num_threads.restype = None
+        L.oracle_set_num_threads.argtypes = [ctypes.c_int]
         L.oracle_evaluate_rk23.restype = ctypes.c_int
         L.oracle_evaluate_rk23.argtypes = [ctypes.c_int64, dp, dp, dp, ctypes.c_void_p,
                                            ctypes.c_int, dp, ctypes.c_double, ctypes.c_double,
@@ -84,6 +87,11 @@ def _f64(a, shape=None):
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_num_threads(nt: int) -> None:
+    """OpenMP threads of the oracle's later calls."""
+    lib().oracle_set_num_threads(int(nt))
 
 
 def params_rows(phases) -> np.ndarray:

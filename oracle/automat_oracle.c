@@ -437,6 +437,16 @@ int oracle_num_threads(void)
 #endif
 }
 
+/* Threads of the following parallel loops (the CPU timing's one-core run). */
+void oracle_set_num_threads(int nt)
+{
+#ifdef _OPENMP
+    if (nt >= 1) omp_set_num_threads(nt);
+#else
+    (void)nt;
+#endif
+}
+
 /* Evaluate n points. eps, a_old: [6][n]; sigma, a_out: [6][n]; tangent
  * [36][n] (row-major 6x6 per point) or NULL; iters [n] or NULL. Returns 0,
  * or -1 on invalid arguments. */
