@@ -24,9 +24,10 @@
 // paper's Theorem on differentiating an integration step); its stress-like
 // image T = C ((s/h) I - Y) enters the error measure beside sigma (42
 // components in the rms), and the result is C_{n+1} = C (I - Y(h)). One
-// lane per point, one wave per block: the stage Hessians Psi'' sit in LDS
-// and Y in the tangent output itself, one column at a time; a step is first
-// measured over all columns and, if accepted, the columns are advanced.
+// lane per point, one wave per block: the stage Hessians Psi'' sit in
+// registers and Y in two LDS buffers; a step makes one pass over the six
+// columns, writing the trial Y to the second buffer, and an accepted step
+// swaps the buffers.
 //
 // The same kernel also runs the lower-order pair of the same section, ode12:
 // explicit Euler embedded in Heun's method, k1 = f(s, y) (recomputed every
@@ -235,36 +236,27 @@ __device__ __forceinline__ void tan_stage(const PhaseConst<Model> &pc, const dou
         for (int r = 0; r < 6; ++r) t -= pc.K[la::pk(q, r)] * v[r];
         b[q] = t;
     }
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        double t = 0.0;
-#pragma unroll
-        for (int r = 0; r < 6; ++r) t += P2m[la::pk(q, r) * kTanLanes] * b[r];
-        Kout[q] = t;
-    }
+    la::symv6(P2m, b, Kout);
 }
 
-// Column j of Y over one step: Y1 (the higher order) and Yh (the embedded
-// lower order) from Yj, with the stage Hessians P2 (stride kTanLanes).
 template <bool BS23>
-__device__ __forceinline__ void tan_column(const PhaseConst<Model> &pc, const double *P2, int j,
-                                           double dt, double th0, double th2, double th3,
+__device__ __forceinline__ void tan_column(const PhaseConst<Model> &pc, const double (*P)[21],
+                                           int j, double dt, double th0, double th2, double th3,
                                            double th4, const double *Yj, double *Y1, double *Yh) {
-    constexpr int S = 21 * kTanLanes;
     double K1[6], K2[6], Yt[6];
-    tan_stage(pc, P2, j, th0, Yj, K1);
+    tan_stage(pc, P[0], j, th0, Yj, K1);
     if constexpr (BS23) {
         double K3[6], K4[6];
 #pragma unroll
         for (int c = 0; c < 6; ++c) Yt[c] = Yj[c] + 0.5 * dt * K1[c];
-        tan_stage(pc, P2 + S, j, th2, Yt, K2);
+        tan_stage(pc, P[1], j, th2, Yt, K2);
 #pragma unroll
         for (int c = 0; c < 6; ++c) Yt[c] = Yj[c] + 0.75 * dt * K2[c];
-        tan_stage(pc, P2 + 2 * S, j, th3, Yt, K3);
+        tan_stage(pc, P[2], j, th3, Yt, K3);
 #pragma unroll
         for (int c = 0; c < 6; ++c)
             Y1[c] = Yj[c] + dt * (2.0 / 9.0 * K1[c] + 1.0 / 3.0 * K2[c] + 4.0 / 9.0 * K3[c]);
-        tan_stage(pc, P2 + 3 * S, j, th4, Y1, K4);
+        tan_stage(pc, P[3], j, th4, Y1, K4);
 #pragma unroll
         for (int c = 0; c < 6; ++c)
             Yh[c] = Yj[c] + dt * (7.0 / 24.0 * K1[c] + 0.25 * K2[c] + 1.0 / 3.0 * K3[c] +
@@ -272,13 +264,12 @@ __device__ __forceinline__ void tan_column(const PhaseConst<Model> &pc, const do
     } else {
 #pragma unroll
         for (int c = 0; c < 6; ++c) Yh[c] = Yj[c] + dt * K1[c];
-        tan_stage(pc, P2 + S, j, th4, Yh, K2);
+        tan_stage(pc, P[1], j, th4, Yh, K2);
 #pragma unroll
         for (int c = 0; c < 6; ++c) Y1[c] = Yj[c] + 0.5 * dt * (K1[c] + K2[c]);
     }
 }
 
-// row i of C (theta e_j - v) for column j
 __device__ __forceinline__ double tan_image(const PhaseConst<Model> &pc, int i, int j, double theta,
                                             const double *v) {
     double t = theta * pc.Cee[la::pk(i, j)];
@@ -287,21 +278,32 @@ __device__ __forceinline__ double tan_image(const PhaseConst<Model> &pc, int i, 
     return t;
 }
 
+// One lane per point, one wave per block. The stage Hessians stay in
+// registers (the kernel may use its SIMD's whole register file, accumulation
+// registers included) and the sensitivity Y in two LDS buffers: every step
+// makes one pass over the six columns, reading Y from one buffer, writing
+// the trial Y1 to the other and adding the columns' share to the error; an
+// accepted step swaps the buffers. Y never goes to global memory; at the end
+// C (I - Y) is written to the tangent output.
 template <bool BS23>
-__global__ __launch_bounds__(kTanLanes) void rk_tan_kernel(const Rk23Args args) {
+__global__ __launch_bounds__(kTanLanes) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void rk_tan_kernel(const Rk23Args args) {
     using PC = PhaseConst<Model>;
-    constexpr int NS = BS23 ? 4 : 2;  // stages whose Psi'' the tangent needs
+    constexpr int NS = BS23 ? 4 : 2;
     extern __shared__ double smem_raw[];
-    double *P2 = smem_raw + threadIdx.x;  // stage m, entry c at [(m * 21 + c) * kTanLanes]
-    PC *tab = reinterpret_cast<PC *>(smem_raw + NS * 21 * kTanLanes);
+    // Y buffers: buffer b, entry k = 6 q + j (Y_qj), lane l at [(36 b + k) 64 + l]
+    double *Ybuf = smem_raw + threadIdx.x;
+    PC *tab = reinterpret_cast<PC *>(smem_raw + 2 * 36 * kTanLanes);
     for (int k = threadIdx.x; k < args.n_phases; k += blockDim.x)
         build_phase_const<Model>(args.phases[k], tab[k], false);
+#pragma unroll
+    for (int k = 0; k < 36; ++k) Ybuf[k * kTanLanes] = 0.0;
     __syncthreads();
     const int64_t n = args.n;
     const double h = args.h, atol = args.atol, rtol = args.rtol;
     const int64_t i = (int64_t)blockIdx.x * kTanLanes + threadIdx.x;
     const bool in = i < n;
-    double *Yg = args.tangent + i;  // Y_qj at [(q * 6 + j) * n] while integrating
+    int cur = 0;  // buffer holding Y
     double e0[6], de[6], y[6];
     bool finite_in = in;
     if (in) {
@@ -320,17 +322,9 @@ __global__ __launch_bounds__(kTanLanes) void rk_tan_kernel(const Rk23Args args) 
     const Model::Phase &p = pc.prm;
     const bool flow = valid && Model::flows(p);
     int status = valid ? 1 : -1;
-    if (in) {
-#pragma unroll 1
-        for (int c = 0; c < 36; ++c) Yg[c * n] = 0.0;
-    }
-    double k1[6], z0[6], P[21];
+    double k1[6], z0[6], P[NS][21];
     if (flow) {
-        if constexpr (BS23) {
-            rk_rhs2(p, e0, de, 0.0, y, k1, P);
-#pragma unroll
-            for (int c = 0; c < 21; ++c) P2[c * kTanLanes] = P[c];
-        }
+        if constexpr (BS23) rk_rhs2(p, e0, de, 0.0, y, k1, P[0]);
         rk_stress(p, e0, de, 0.0, y, z0);
     }
     double s = 0.0, dt = h, fmx = 5.0;
@@ -353,34 +347,24 @@ __global__ __launch_bounds__(kTanLanes) void rk_tan_kernel(const Rk23Args args) 
             double yt[6], k2[6], k3[6];
 #pragma unroll
             for (int c = 0; c < 6; ++c) yt[c] = y[c] + 0.5 * dt * k1[c];
-            rk_rhs2(p, e0, de, th2, yt, k2, P);
-#pragma unroll
-            for (int c = 0; c < 21; ++c) P2[(21 + c) * kTanLanes] = P[c];
+            rk_rhs2(p, e0, de, th2, yt, k2, P[1]);
 #pragma unroll
             for (int c = 0; c < 6; ++c) yt[c] = y[c] + 0.75 * dt * k2[c];
-            rk_rhs2(p, e0, de, th3, yt, k3, P);
-#pragma unroll
-            for (int c = 0; c < 21; ++c) P2[(42 + c) * kTanLanes] = P[c];
+            rk_rhs2(p, e0, de, th3, yt, k3, P[2]);
 #pragma unroll
             for (int c = 0; c < 6; ++c)
                 y1[c] = y[c] + dt * (2.0 / 9.0 * k1[c] + 1.0 / 3.0 * k2[c] + 4.0 / 9.0 * k3[c]);
-            rk_rhs2(p, e0, de, th4, y1, k4, P);
-#pragma unroll
-            for (int c = 0; c < 21; ++c) P2[(63 + c) * kTanLanes] = P[c];
+            rk_rhs2(p, e0, de, th4, y1, k4, P[3]);
 #pragma unroll
             for (int c = 0; c < 6; ++c)
                 yh[c] = y[c] + dt * (7.0 / 24.0 * k1[c] + 0.25 * k2[c] + 1.0 / 3.0 * k3[c] +
                                      0.125 * k4[c]);
         } else {
             double k2[6];
-            rk_rhs2(p, e0, de, th0, y, k1, P);
-#pragma unroll
-            for (int c = 0; c < 21; ++c) P2[c * kTanLanes] = P[c];
+            rk_rhs2(p, e0, de, th0, y, k1, P[0]);
 #pragma unroll
             for (int c = 0; c < 6; ++c) yh[c] = y[c] + dt * k1[c];
-            rk_rhs2(p, e0, de, th4, yh, k2, P);
-#pragma unroll
-            for (int c = 0; c < 21; ++c) P2[(21 + c) * kTanLanes] = P[c];
+            rk_rhs2(p, e0, de, th4, yh, k2, P[1]);
 #pragma unroll
             for (int c = 0; c < 6; ++c) y1[c] = y[c] + 0.5 * dt * (k1[c] + k2[c]);
         }
@@ -393,19 +377,26 @@ __global__ __launch_bounds__(kTanLanes) void rk_tan_kernel(const Rk23Args args) 
             const double r = (z1[c] - zh[c]) / (atol + rtol * fmax(fabs(z0[c]), fabs(z1[c])));
             sum += r * r;
         }
-        // the tangent's share of the error, one column of Y at a time
-#pragma unroll 1
+        const double *Yc = Ybuf + 36 * kTanLanes * cur;
+        double *Yn = Ybuf + 36 * kTanLanes * (1 - cur);
+        // columns are independent: ode12 works on three at a time (more
+        // independent operations in flight); ode23's four stage Hessians
+        // leave registers for one
+        constexpr int kColUnroll = BS23 ? 1 : 3;
+#pragma unroll kColUnroll
         for (int j = 0; j < 6; ++j) {
             double Yj[6], Y1[6], Yh[6];
 #pragma unroll
-            for (int q = 0; q < 6; ++q) Yj[q] = Yg[(q * 6 + j) * n];
-            tan_column<BS23>(pc, P2, j, dt, th0, th2, th3, th4, Yj, Y1, Yh);
+            for (int q = 0; q < 6; ++q) Yj[q] = Yc[(q * 6 + j) * kTanLanes];
+            tan_column<BS23>(pc, P, j, dt, th0, th2, th3, th4, Yj, Y1, Yh);
+#pragma unroll
+            for (int q = 0; q < 6; ++q) Yn[(q * 6 + j) * kTanLanes] = Y1[q];
 #pragma unroll
             for (int r = 0; r < 6; ++r) {
                 const double t0 = tan_image(pc, r, j, th0, Yj);
                 const double t1 = tan_image(pc, r, j, th4, Y1);
                 const double tq = tan_image(pc, r, j, th4, Yh);
-                const double e = (t1 - tq) / (atol + rtol * fmax(fabs(t0), fabs(t1)));
+                const double e = (t1 - tq) * fm::rcp(atol + rtol * fmax(fabs(t0), fabs(t1)));
                 sum += e * e;
             }
         }
@@ -415,27 +406,18 @@ __global__ __launch_bounds__(kTanLanes) void rk_tan_kernel(const Rk23Args args) 
             fac = BS23 ? 0.9 * fm::exp(-fm::log(err) * (1.0 / 3.0)) : 0.9 / sqrt(err);
         fac = fmin(fmx, fmax(0.2, fac));
         if (err <= 1.0) {
-            // advance the columns of Y with the accepted step
-#pragma unroll 1
-            for (int j = 0; j < 6; ++j) {
-                double Yj[6], Y1[6], Yh[6];
-#pragma unroll
-                for (int q = 0; q < 6; ++q) Yj[q] = Yg[(q * 6 + j) * n];
-                tan_column<BS23>(pc, P2, j, dt, th0, th2, th3, th4, Yj, Y1, Yh);
-#pragma unroll
-                for (int q = 0; q < 6; ++q) Yg[(q * 6 + j) * n] = Y1[q];
-            }
+            cur = 1 - cur;
             ++accepted;
             s = last ? h : s + dt;
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
                 y[c] = y1[c];
-                if (BS23) k1[c] = k4[c];  // first same as last
+                if (BS23) k1[c] = k4[c];
                 z0[c] = z1[c];
             }
             if constexpr (BS23) {
 #pragma unroll
-                for (int c = 0; c < 21; ++c) P2[c * kTanLanes] = P2[(63 + c) * kTanLanes];
+                for (int c = 0; c < 21; ++c) P[0][c] = P[3][c];
             }
             dt *= fac;
             fmx = 5.0;
@@ -461,18 +443,20 @@ __global__ __launch_bounds__(kTanLanes) void rk_tan_kernel(const Rk23Args args) 
     }
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-        args.sigma[c * n + i] = sig[c];
-        args.a_out[c * n + i] = y[c];
+        __builtin_nontemporal_store(sig[c], args.sigma + c * n + i);
+        __builtin_nontemporal_store(y[c], args.a_out + c * n + i);
     }
-    // C_{n+1} = C (I - Y), column by column in place of Y
+    // C_{n+1} = C (I - Y(h))
+    const double *Yc = Ybuf + 36 * kTanLanes * cur;
 #pragma unroll 1
     for (int j = 0; j < 6; ++j) {
         double Yj[6];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) Yj[q] = Yg[(q * 6 + j) * n];
+        for (int q = 0; q < 6; ++q) Yj[q] = Yc[(q * 6 + j) * kTanLanes];
 #pragma unroll
         for (int r = 0; r < 6; ++r)
-            Yg[(r * 6 + j) * n] = valid ? tan_image(pc, r, j, 1.0, Yj) : NAN;
+            __builtin_nontemporal_store(valid ? tan_image(pc, r, j, 1.0, Yj) : NAN,
+                                        args.tangent + (r * 6 + j) * n + i);
     }
     if (args.steps) args.steps[i] = status;
     if (args.nonconv && status < 0) atomicAdd(args.nonconv, 1ull);
@@ -519,10 +503,11 @@ static int32_t launch_rk(bool bs23, int64_t n, const double *eps_n, const double
     args.max_steps = max_steps;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (tangent_out) {
-        // one wave per block, stage Hessians in LDS, Y in the tangent output
+        // one wave per block: the stage Hessians in registers, the
+        // sensitivity's two buffers and the phase table in LDS
         const int64_t blocks = (n + kTanLanes - 1) / kTanLanes;
         if (blocks > 0x7fffffffLL) return AUTOMAT_EINVAL;
-        const size_t smem = (size_t)(bs23 ? 4 : 2) * 21 * kTanLanes * sizeof(double) +
+        const size_t smem = (size_t)2 * 36 * kTanLanes * sizeof(double) +
                             (size_t)args.n_phases * sizeof(PhaseConst<Model>);
         if (bs23)
             hipLaunchKernelGGL(rk_tan_kernel<true>, dim3((unsigned)blocks), dim3(kTanLanes), smem,
