@@ -279,6 +279,8 @@ def main():
     ap.add_argument("--no-tangent", action="store_true", help="skip the tangent variant")
     ap.add_argument("--serve-requests", type=int, default=1000,
                     help="requests in the serving stream (0 skips the serving leg)")
+    ap.add_argument("--serve-cap", type=int, default=1 << 24,
+                    help="points per batched launch (latency-aware batch shaping; 0 = unbounded)")
     ap.add_argument("--serve-workers", type=int, default=8,
                     help="host processes generating the requests' microstructures")
     ap.add_argument("--ms-steps", type=int, default=20,
@@ -424,6 +426,18 @@ def main():
                            "ms_per_step": ms_cv, "value": n / (ms_cv * 1e-3), "unit": "updates/s",
                            "automatic_over_conventional_time": ms / ms_cv}
     log(f"[bench] conventional: {ms_cv:.3f} ms/step (automatic / conventional = {ms / ms_cv:.2f})")
+    if not args.no_tangent:
+        def step_cvt():
+            api.evaluate_conventional(eps, a_old, phase, ps.phases, ps.h, ps.tol, ps.max_iter,
+                                      sigma_out=sigma, a_out=a_new, tangent=True,
+                                      tangent_out=tan_out)
+        tct, _, _ = time_calls(step_cvt, max(5, args.steps // 2), 2, stream)
+        cv_t = tct / max(5, args.steps // 2)
+        out["conventional"]["tangent_ms_per_step"] = cv_t
+        if "tangent" in out:
+            out["conventional"]["automatic_over_conventional_time_tangent"] = (
+                out["tangent"]["ms_per_step"] / cv_t)
+        log(f"[bench] conventional with tangent: {cv_t:.3f} ms/step")
 
     # the paper's semi-automatic strategy: the same Newton solve and tangent
     # with hand-derived partials of omega and Psi instead of AD
@@ -539,11 +553,14 @@ def main():
         torch.cuda.empty_cache()
         sv = {"workload": f"{len(serve_reqs)} requests, Poisson arrivals 200/s, cube side "
                           "log-uniform in [32, 256], fibre or sphere microstructure, phase "
-                          "parameters jittered +-10 %, 1-10 load steps each, HBM budget 200 GB"}
+                          "parameters jittered +-10 %, 1-10 load steps each, HBM budget 200 GB; "
+                          f"batched launches capped at {args.serve_cap} points, least remaining "
+                          "work first"}
         for saturate in (False, True):
             for sequential in (False, True):
                 r = serve.replay(serve_reqs, serve_fields, sequential=sequential,
-                                 saturate=saturate)
+                                 saturate=saturate,
+                                 max_batch_points=0 if sequential else args.serve_cap)
                 key = ("saturated_" if saturate else "poisson_") + r["mode"]
                 sv[key] = r
                 log(f"[bench] serving {key}: {r['throughput']:.3e} updates/s, "

@@ -6,11 +6,15 @@
 // of the memory budget. Requests are admitted in arrival order while their
 // device block (phase ids, internal variables, stress: 97 B per point, plus
 // the phase tables) fits in the arena (first-fit, coalescing). Every round
-// builds one batch with the next load step of every admitted request (a
-// ragged table of segments) and launches one kernel over all of them; while
-// it runs, requests that arrived meanwhile are admitted and their inputs
-// uploaded on the second stream (their first batch waits for an event).
-// Finished requests return their block at once. In sequential mode only one
+// builds one batch with the next load step of admitted requests (a ragged
+// table of segments) and launches one kernel over all of them; while it
+// runs, requests that arrived meanwhile are admitted and their inputs
+// uploaded on the second stream (their first batch waits for an event). A
+// batch takes the requests with the least remaining work first (points
+// times load steps left) up to an optional point cap, with aging so that no
+// request waits more than a few batches: small and nearly finished requests
+// are not held behind large ones. Finished requests return their block at
+// once. In sequential mode only one
 // request is admitted at a time (one launch and one wait per load step),
 // which is the per-request baseline.
 //
@@ -352,6 +356,7 @@ struct Req {
     unsigned long long *d_nonconv = nullptr;
     hipEvent_t ready = nullptr;  // uploads and table build done
     int32_t steps_done = 0;
+    int64_t last_round = 0;      // round of the last batch that took a step of it
     double t_arrival = 0, t_admit = 0, t_done = 0;
     int32_t status = 0;
 };
@@ -382,7 +387,7 @@ struct automat_server {
     Arena arena;
     Segment *d_segs = nullptr, *h_segs = nullptr;
     int seg_cap = 0;
-    size_t rr = 0;  // round-robin start among active requests
+    int64_t round = 0;  // batches built so far
     // statistics
     int64_t launches = 0, updates = 0;
     double busy_s = 0;
@@ -396,6 +401,7 @@ static void take_admissible(automat_server *s, std::vector<Req *> &fresh) {
         Req *q = s->pending.front();
         if (!s->arena.alloc(q->lay.total, &q->off)) break;
         s->pending.pop_front();
+        q->last_round = s->round;
         s->used += q->lay.total;
         s->active.push_back(q);
         fresh.push_back(q);
@@ -483,9 +489,12 @@ static void admit(automat_server *s, std::vector<Req *> &fresh) {
     fresh.clear();
 }
 
+// batches a request may be left out of before it goes first
+constexpr int64_t kAging = 16;
+
 static void worker_loop(automat_server *s) {
     (void)hipSetDevice(s->device);
-    std::vector<Req *> batch, fresh;
+    std::vector<Req *> batch, fresh, order;
     for (;;) {
         {
             std::unique_lock<std::mutex> lock(s->mu);
@@ -506,21 +515,31 @@ static void worker_loop(automat_server *s) {
             take_admissible(s, fresh);
         }
         admit(s, fresh);
-        // one batch: the next load step of active requests, round-robin
-        // from s->rr while the point budget lasts (at least one request)
+        // one batch: the next load step of active requests while the point
+        // budget lasts (at least one request). Latency-aware order: the
+        // least remaining work (points x steps left) first, so that small
+        // and nearly finished requests are not held behind large ones; a
+        // request left out of kAging consecutive batches goes first.
         batch.clear();
         {
             std::lock_guard<std::mutex> lock(s->mu);
-            const size_t na = s->active.size();
+            order.assign(s->active.begin(), s->active.end());
+            const int64_t rnd = ++s->round;
+            auto starved = [&](const Req *q) { return rnd - q->last_round > kAging; };
+            auto remaining = [](const Req *q) { return q->r.n * (int64_t)(q->r.steps - q->steps_done); };
+            std::stable_sort(order.begin(), order.end(), [&](const Req *a, const Req *b) {
+                if (starved(a) != starved(b)) return starved(a);
+                return remaining(a) < remaining(b);
+            });
             int64_t pts = 0;
-            for (size_t k = 0; k < na && batch.size() < (size_t)kMaxSegs; ++k) {
-                Req *q = s->active[(s->rr + k) % na];
+            for (Req *q : order) {
+                if (batch.size() >= (size_t)kMaxSegs) break;
                 if (!batch.empty() && s->max_batch_points > 0 && pts + q->r.n > s->max_batch_points)
                     continue;
                 batch.push_back(q);
                 pts += q->r.n;
+                q->last_round = rnd;
             }
-            if (na) s->rr = (s->rr + batch.size()) % na;
         }
         if (batch.empty()) continue;
         if ((int)batch.size() > s->seg_cap) {
