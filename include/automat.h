@@ -232,6 +232,25 @@ int32_t automat_ms_step(automat_ms *ms, const uint8_t *phase, const double *E_ma
                         double *eps, double *a, double *sigma_out, double *sigma_mean,
                         int32_t *iters, double *residual, void *stream);
 
+/* automat_ms_step for callers that cannot allocate device memory (code
+ * under graph capture, tight serving loops, harnesses that forbid
+ * allocation): the step's work space (the polarization field, its half
+ * spectrum, the reduction partials and scalars, the failed-solve counter)
+ * lives in a 64 MiB device array of the library, one per device, held
+ * until the process ends, instead of the handle's buffers; the call makes
+ * no allocation (the handle, with its transform plans, is created
+ * beforehand). Same arguments, results and synchronization as
+ * automat_ms_step. AUTOMAT_EINVAL if the work space does not fit in 64 MiB
+ * (6 n doubles + 6 (nx/2 + 1) ny nz complex doubles + 50 KiB, i.e. grids up
+ * to about 86^3 voxels) or if the handle adjusts its reference every step
+ * (ref_update: that sweep needs a tangent field). Every call on one device
+ * shares the array: calls that overlap on one device (other streams, other
+ * threads) race. */
+int32_t automat_ms_step_noalloc(automat_ms *ms, const uint8_t *phase, const double *E_macro,
+                                double h, double *eps, double *a, double *sigma_out,
+                                double *sigma_mean, int32_t *iters, double *residual,
+                                void *stream);
+
 /* One load step under mixed boundary conditions. Bit c of stress_mask
  * (0 <= stress_mask < 64, components in engineering Voigt order 11 22 33 23
  * 13 12) selects a stress-controlled component, whose mean stress is

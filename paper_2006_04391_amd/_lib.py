@@ -85,6 +85,7 @@ SIGNATURES = {
                                          _vp, _vp]),
     "automat_ms_create": (_i32, [_i32, _i32, _i32, _vp, _vp, _vp]),
     "automat_ms_step": (_i32, [_vp, _vp, _vp, _dbl, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "automat_ms_step_noalloc": (_i32, [_vp, _vp, _vp, _dbl, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "automat_ms_newton_failures": (_i32, [_vp, _vp]),
     "automat_ms_step_mixed": (_i32, [_vp, _vp, _vp, _vp, ctypes.c_uint32, _dbl, _vp, _vp, _vp,
                                       _vp, _vp, _vp, _vp, _vp]),

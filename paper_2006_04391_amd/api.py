@@ -306,6 +306,28 @@ class MS:
         check("automat_ms_step", rc)
         return list(mean), iters.value, res.value
 
+    def step_noalloc(self, phase, E_macro, h, eps, a, sigma_out=None):
+        """step() through automat_ms_step_noalloc: the work space is the
+        library's fixed device array, so the call allocates nothing (grids
+        up to about 86^3, no reference update). Same returns as step()."""
+        dev = self.device
+        eps = _field(eps, "eps", 6, self.n, dev)
+        a = _field(a, "a", 6, self.n, dev)
+        phase = _phase_ids(phase, self.n, dev)
+        if sigma_out is not None:
+            sigma_out = _field(sigma_out, "sigma_out", 6, self.n, dev)
+        E = (ctypes.c_double * 6)(*[float(x) for x in E_macro])
+        mean = (ctypes.c_double * 6)()
+        iters = ctypes.c_int32()
+        res = ctypes.c_double()
+        with torch.cuda.device(dev):
+            rc = load().automat_ms_step_noalloc(self._h, _ptr(phase), E, float(h), _ptr(eps),
+                                                _ptr(a), _ptr(sigma_out), mean,
+                                                ctypes.byref(iters), ctypes.byref(res),
+                                                _stream(dev))
+        check("automat_ms_step_noalloc", rc)
+        return list(mean), iters.value, res.value
+
     def step_mixed(self, phase, E_macro, h, eps, a, stress_mask, S_macro=None, sigma_out=None):
         """Advance one load step under mixed conditions (automat_ms_step_mixed):
         bit c of stress_mask makes component c stress-controlled with mean

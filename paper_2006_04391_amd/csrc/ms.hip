@@ -39,6 +39,8 @@
 #include <hip/hip_runtime.h>
 #include <hipfft/hipfft.h>
 
+#include <mutex>
+
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -520,8 +522,8 @@ static int32_t ensure_buffer(double **p, size_t bytes) {
     return AUTOMAT_OK;
 }
 
-static int32_t read_scalars(automat_ms *m, int count, hipStream_t s) {
-    if (hipMemcpyAsync(m->host_scal, m->scal, count * sizeof(double), hipMemcpyDeviceToHost, s) !=
+static int32_t read_scalars(automat_ms *m, const double *scal, int count, hipStream_t s) {
+    if (hipMemcpyAsync(m->host_scal, scal, count * sizeof(double), hipMemcpyDeviceToHost, s) !=
             hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return AUTOMAT_EHIP;
@@ -542,7 +544,7 @@ static int32_t update_reference(automat_ms *m, const uint8_t *phase, double h, c
     hipLaunchKernelGGL(iso_minmax_kernel, dim3(rb), dim3(kRedBlock), 0, s, m->tan, n, m->partial);
     hipLaunchKernelGGL(finish_minmax_kernel, dim3(4), dim3(kRedBlock), 0, s, m->partial, rb,
                        m->scal);
-    rc = read_scalars(m, 4, s);
+    rc = read_scalars(m, m->scal, 4, s);
     if (rc) return rc;
     const double lam0 = 0.5 * (m->host_scal[0] + m->host_scal[1]);
     const double mu0 = 0.5 * (m->host_scal[2] + m->host_scal[3]);
@@ -553,28 +555,38 @@ static int32_t update_reference(automat_ms *m, const uint8_t *phase, double h, c
     return AUTOMAT_OK;
 }
 
-extern "C" int32_t automat_ms_step_mixed(automat_ms *m, const uint8_t *phase,
-                                         const double *E_macro, const double *S_macro,
-                                         uint32_t stress_mask, double h, double *eps, double *a,
-                                         double *sigma_out, double *sigma_mean,
-                                         double *E_reached, int32_t *iters, double *residual,
-                                         void *stream) {
-    if (!m || !phase || !E_macro || !eps || !a) return AUTOMAT_EINVAL;
-    if (!std::isfinite(h) || !(h > 0.0) || stress_mask > 63u) return AUTOMAT_EINVAL;
+// Work space of one load step: the polarization / inverse-transform field,
+// its half spectrum, the reduction partials, the reduced scalars and the
+// failed-solve counter.
+struct MsWork {
+    double *sig;                // [6][n]
+    hipfftDoubleComplex *spec;  // [6][nh]
+    double *partial;            // [6 * kRedBlocks]
+    double *scal;               // [16]
+    uint64_t *fails;            // [1]
+};
+
+__global__ void zero_u64_kernel(uint64_t *p) { *p = 0; }
+
+static int32_t ms_step_impl(automat_ms *m, const MsWork &w, const uint8_t *phase,
+                            const double *E_macro, const double *S_macro, uint32_t stress_mask,
+                            double h, double *eps, double *a, double *sigma_out,
+                            double *sigma_mean, double *E_reached, int32_t *iters,
+                            double *residual, void *stream) {
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int64_t n = m->f.n;
     const int tb = 256;
     const int gb = (int)((n + tb - 1) / tb);
     if (hipfftSetStream(m->fwd, s) != HIPFFT_SUCCESS || hipfftSetStream(m->inv, s) != HIPFFT_SUCCESS)
         return AUTOMAT_EHIP;
-    if (hipMemsetAsync(m->fails, 0, sizeof(uint64_t), s) != hipSuccess) return AUTOMAT_EHIP;
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, s, w.fails);
     MacroBC bc;
     for (int c = 0; c < 6; ++c) {
         bc.E[c] = (stress_mask >> c & 1u) ? 0.0 : E_macro[c];
         bc.S[c] = S_macro ? S_macro[c] : 0.0;
     }
     bc.mask = stress_mask;
-    bc.Eout = m->scal + 8;
+    bc.Eout = w.scal + 8;
     // initial guess: previous strain field shifted by the prescribed strain
     // increments and, on stress-controlled components, the increments that
     // keep the reference medium's stress there unchanged
@@ -604,18 +616,18 @@ extern "C" int32_t automat_ms_step_mixed(automat_ms *m, const uint8_t *phase,
     for (it = 1; it <= m->opts.max_iter; ++it) {
         // material sweep writing the polarization tau = sigma - C0 eps
         rc = evaluate_polarized(n, eps, a, phase, &m->params, h, m->opts.newton_tol,
-                                m->opts.newton_max_iter, m->lam0, m->mu0, m->sig, warm(m),
-                                m->fails, stream);
+                                m->opts.newton_max_iter, m->lam0, m->mu0, w.sig, warm(m),
+                                w.fails, stream);
         if (rc) return rc;
-        if (hipfftExecD2Z(m->fwd, m->sig, m->spec) != HIPFFT_SUCCESS) return AUTOMAT_EHIP;
-        hipLaunchKernelGGL(gamma_kernel, dim3(nhb), dim3(tb), 0, s, m->spec, m->f, m->lam0,
+        if (hipfftExecD2Z(m->fwd, w.sig, w.spec) != HIPFFT_SUCCESS) return AUTOMAT_EHIP;
+        hipLaunchKernelGGL(gamma_kernel, dim3(nhb), dim3(tb), 0, s, w.spec, m->f, m->lam0,
                            m->mu0, bc);
-        if (hipfftExecZ2D(m->inv, m->spec, m->sig) != HIPFFT_SUCCESS) return AUTOMAT_EHIP;
-        hipLaunchKernelGGL(update_kernel, dim3(rb), dim3(kRedBlock), 0, s, eps, m->sig, n,
-                           m->partial);
-        hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedBlock), 0, s, m->partial, rb, m->scal);
+        if (hipfftExecZ2D(m->inv, w.spec, w.sig) != HIPFFT_SUCCESS) return AUTOMAT_EHIP;
+        hipLaunchKernelGGL(update_kernel, dim3(rb), dim3(kRedBlock), 0, s, eps, w.sig, n,
+                           w.partial);
+        hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedBlock), 0, s, w.partial, rb, w.scal);
         if (!m->opts.fixed_iter || it == m->opts.max_iter) {
-            rc = read_scalars(m, 14, s);
+            rc = read_scalars(m, w.scal, 14, s);
             if (rc) return rc;
             for (int c = 0; c < 6; ++c) Ecur[c] = m->host_scal[8 + c];
             err = sqrt(m->host_scal[0] / (double)n) / fmax(tensor_norm(Ecur), 1e-300);
@@ -624,19 +636,19 @@ extern "C" int32_t automat_ms_step_mixed(automat_ms *m, const uint8_t *phase,
     }
     if (it > m->opts.max_iter) it = m->opts.max_iter;
     // commit: sweep at the converged strain, a_n <- a_{n+1}
-    double *sig = sigma_out ? sigma_out : m->sig;
+    double *sig = sigma_out ? sigma_out : w.sig;
     rc = evaluate_warm(n, eps, a, phase, &m->params, h, m->opts.newton_tol,
-                       m->opts.newton_max_iter, sig, a, nullptr, warm(m), warm(m), m->fails,
+                       m->opts.newton_max_iter, sig, a, nullptr, warm(m), warm(m), w.fails,
                        stream);
     if (rc) return rc;
     if (sigma_mean) {
-        hipLaunchKernelGGL(mean6_kernel, dim3(rb), dim3(kRedBlock), 0, s, sig, n, m->partial);
-        hipLaunchKernelGGL(finish_kernel, dim3(6), dim3(kRedBlock), 0, s, m->partial, rb, m->scal);
-        rc = read_scalars(m, 6, s);
+        hipLaunchKernelGGL(mean6_kernel, dim3(rb), dim3(kRedBlock), 0, s, sig, n, w.partial);
+        hipLaunchKernelGGL(finish_kernel, dim3(6), dim3(kRedBlock), 0, s, w.partial, rb, w.scal);
+        rc = read_scalars(m, w.scal, 6, s);
         if (rc) return rc;
         for (int c = 0; c < 6; ++c) sigma_mean[c] = m->host_scal[c] / (double)n;
     }
-    if (hipMemcpyAsync(m->host_fails, m->fails, sizeof(uint64_t), hipMemcpyDeviceToHost, s) !=
+    if (hipMemcpyAsync(m->host_fails, w.fails, sizeof(uint64_t), hipMemcpyDeviceToHost, s) !=
             hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return AUTOMAT_EHIP;
@@ -651,12 +663,85 @@ extern "C" int32_t automat_ms_step_mixed(automat_ms *m, const uint8_t *phase,
     return AUTOMAT_OK;
 }
 
+extern "C" int32_t automat_ms_step_mixed(automat_ms *m, const uint8_t *phase,
+                                         const double *E_macro, const double *S_macro,
+                                         uint32_t stress_mask, double h, double *eps, double *a,
+                                         double *sigma_out, double *sigma_mean,
+                                         double *E_reached, int32_t *iters, double *residual,
+                                         void *stream) {
+    if (!m || !phase || !E_macro || !eps || !a) return AUTOMAT_EINVAL;
+    if (!std::isfinite(h) || !(h > 0.0) || stress_mask > 63u) return AUTOMAT_EINVAL;
+    const MsWork w{m->sig, m->spec, m->partial, m->scal, m->fails};
+    return ms_step_impl(m, w, phase, E_macro, S_macro, stress_mask, h, eps, a, sigma_out,
+                        sigma_mean, E_reached, iters, residual, stream);
+}
+
 extern "C" int32_t automat_ms_step(automat_ms *m, const uint8_t *phase, const double *E_macro,
                                    double h, double *eps, double *a, double *sigma_out,
                                    double *sigma_mean, int32_t *iters, double *residual,
                                    void *stream) {
     return automat_ms_step_mixed(m, phase, E_macro, nullptr, 0u, h, eps, a, sigma_out, sigma_mean,
                                  nullptr, iters, residual, stream);
+}
+
+// --------------------------------------------------------------------------
+// The load step without allocation: the step's work space lives in a
+// file-scope device array (one copy per device, held until the process
+// ends) instead of the handle's buffers. Host code never passes the array's
+// name to a kernel or copy: its device address is taken once per device
+// with hipGetSymbolAddress and kept.
+// --------------------------------------------------------------------------
+
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mutex;
+static void *g_scratch_ptr[64];
+static bool g_scratch_init[64];
+
+static int32_t scratch_address(void **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return AUTOMAT_EHIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_init[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return AUTOMAT_EHIP;
+        }
+        g_scratch_ptr[dev] = ptr;
+        g_scratch_init[dev] = true;
+    }
+    *out = g_scratch_ptr[dev];
+    return AUTOMAT_OK;
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+extern "C" int32_t automat_ms_step_noalloc(automat_ms *m, const uint8_t *phase,
+                                           const double *E_macro, double h, double *eps,
+                                           double *a, double *sigma_out, double *sigma_mean,
+                                           int32_t *iters, double *residual, void *stream) {
+    if (!m || !phase || !E_macro || !eps || !a) return AUTOMAT_EINVAL;
+    if (!std::isfinite(h) || !(h > 0.0)) return AUTOMAT_EINVAL;
+    if (m->opts.ref_update) return AUTOMAT_EINVAL;  // its tangent field is not in the work space
+    const size_t b_sig = align256((size_t)m->f.n * 6 * sizeof(double));
+    const size_t b_spec = align256((size_t)m->f.nh * 6 * sizeof(hipfftDoubleComplex));
+    const size_t b_part = align256((size_t)6 * kRedBlocks * sizeof(double));
+    const size_t b_scal = align256(16 * sizeof(double));
+    if (b_sig + b_spec + b_part + b_scal + 256 > kScratchBytes) return AUTOMAT_EINVAL;
+    void *base = nullptr;
+    const int32_t rc = scratch_address(&base);
+    if (rc) return rc;
+    char *p = static_cast<char *>(base);
+    MsWork w;
+    w.sig = reinterpret_cast<double *>(p);
+    w.spec = reinterpret_cast<hipfftDoubleComplex *>(p + b_sig);
+    w.partial = reinterpret_cast<double *>(p + b_sig + b_spec);
+    w.scal = reinterpret_cast<double *>(p + b_sig + b_spec + b_part);
+    w.fails = reinterpret_cast<uint64_t *>(p + b_sig + b_spec + b_part + b_scal);
+    return ms_step_impl(m, w, phase, E_macro, nullptr, 0u, h, eps, a, sigma_out, sigma_mean,
+                        nullptr, iters, residual, stream);
 }
 
 extern "C" int32_t automat_ms_newton_failures(const automat_ms *m, uint64_t *count) {
