@@ -1,8 +1,8 @@
 """Build libautomat.so (HIP, gfx950) in-tree with hipcc.
 
 The library is compiled for gfx950 only. Packed-FP32 instructions are
-disabled (FP32 is not used on this path, the flag keeps the compiler from
-generating them anywhere).
+disabled everywhere, the FP32 evaluation kernel included: the compiler then
+issues one FP32 operation per instruction instead of forming packed pairs.
 """
 from __future__ import annotations
 
