@@ -69,9 +69,11 @@ def test_laminate_exact():
     np.testing.assert_allclose(r["sigma_mean"], ref, rtol=1e-8, atol=1e-8 * np.abs(ref).max())
 
 
-@pytest.mark.parametrize("shape", [(12, 12, 12), (6, 10, 12)])
+@pytest.mark.parametrize("shape", [(12, 12, 12), (6, 10, 12), (16, 12, 10), (32, 6, 9),
+                                   (8, 8, 8)])
 def test_lockstep_parity_viscoplastic(shape):
-    """Fixed iteration counts on both sides: fields agree to rounding."""
+    """Fixed iteration counts on both sides: fields agree to rounding (odd
+    and even extents, power-of-two and other lengths along every axis)."""
     nz, ny, nx = shape
     rng = np.random.default_rng(7)
     phase = (rng.random(nz * ny * nx) < 0.2).astype(np.uint8)
@@ -184,7 +186,8 @@ def test_mixed_laminate_exact(mask):
 
 
 @pytest.mark.parametrize("shape,upd", [((12, 12, 12), True), ((6, 10, 12), True),
-                                       ((7, 9, 10), False)])
+                                       ((7, 9, 10), False), ((16, 10, 12), True),
+                                       ((8, 7, 6), False)])
 def test_lockstep_parity_mixed(shape, upd):
     """Uniaxial tension then compression under mixed conditions, the
     reference adjusted every step: fixed iteration counts on both sides,
