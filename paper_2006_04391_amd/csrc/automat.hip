@@ -235,7 +235,13 @@ void gsm_eval_kernel(const EvalArgs args) {
             // batch in lane order, which keeps the output stores coalesced
             const bool queue = kCompact ? in_range && valid && M::flows(pc.prm) : in_range;
             if (kCompact && in_range && !queue) {
-                // no flow: a_{n+1} = a_n, elastic stress and stiffness
+                // no flow: a_{n+1} = a_n, elastic stress and stiffness.
+                // Ordinary (cached) stores: these points share their 64-byte
+                // lines with flowing points of the same chunk, which are
+                // written one Newton batch later; held in L2, the two parts
+                // leave as one line. Nontemporal stores here send the
+                // partial lines to memory separately, which costs write
+                // traffic and time.
                 double sig[6];
                 if (valid) {
                     M::stress(pc.prm, e, a, sig);
@@ -245,12 +251,10 @@ void gsm_eval_kernel(const EvalArgs args) {
                     for (int c = 0; c < 6; ++c) sig[c] = a[c] = NAN;
                 }
 #pragma unroll
-                for (int c = 0; c < 6; ++c)
-                    __builtin_nontemporal_store(sig[c], args.sigma + c * n + i);
+                for (int c = 0; c < 6; ++c) args.sigma[c * n + i] = sig[c];
                 if (args.a_out) {
 #pragma unroll
-                    for (int c = 0; c < 6; ++c)
-                        __builtin_nontemporal_store(a[c], args.a_out + c * n + i);
+                    for (int c = 0; c < 6; ++c) args.a_out[c * n + i] = a[c];
                 }
                 if (WARM && args.delta_out) {
 #pragma unroll

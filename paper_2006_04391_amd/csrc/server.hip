@@ -247,7 +247,9 @@ void serve_batch_kernel(const Segment *segs, const int32_t *starts, int nseg, in
                     }
                 }
 #pragma unroll
-                for (int c = 0; c < 6; ++c) __builtin_nontemporal_store(sig[c], sg.sigma + c * n + i);
+                // cached stores, so that the line merges in L2 with the
+                // flowing points written one Newton batch later
+                for (int c = 0; c < 6; ++c) sg.sigma[c * n + i] = sig[c];
             }
             count_failures(sg.nonconv, !valid);
         }
