@@ -47,6 +47,7 @@
 
 #include "automat.h"
 #include "host_common.hpp"
+#include "slab_fft.hpp"
 
 namespace automat {
 namespace {
@@ -125,15 +126,20 @@ __device__ __forceinline__ void gamma_add(double q1, double q2, double q3,
 
 // eps^ = -Gamma0 : tau^ on the half spectrum (in place); eps^(0) = E * n
 // with E from the macroscopic conditions (above).
+// Value c of frequency (kx, ky, kz) sits at spec[c * cs + kz * zs + ky * nxh
+// + kx]: cs = nh, zs = ny * nxh for component-major spectra (the 3-D
+// transforms), cs = ny * nxh, zs = 6 cs for plane-major ones (the slab
+// transforms).
 __global__ void gamma_kernel(hipfftDoubleComplex *spec, MsField f, double lam0, double mu0,
-                             MacroBC bc) {
+                             MacroBC bc, int64_t cs, int64_t zs) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= f.nh) return;
     const int nxh = f.nx / 2 + 1;
     const int kx = (int)(idx % nxh);
     const int ky = (int)((idx / nxh) % f.ny);
     const int kz = (int)(idx / ((int64_t)nxh * f.ny));
-    const int64_t s = f.nh;
+    const int64_t s = cs;
+    const int64_t at = (int64_t)kz * zs + (int64_t)ky * nxh + kx;
     if (kx == 0 && ky == 0 && kz == 0) {
         const double nn = (double)f.n;
         double r[6], E[6];
@@ -151,7 +157,7 @@ __global__ void gamma_kernel(hipfftDoubleComplex *spec, MsField f, double lam0, 
     const bool n3 = (f.nz % 2 == 0) && kz == f.nz / 2;
     const int nonzero = (kx != 0) + (ky != 0) + (kz != 0);
     hipfftDoubleComplex t[6];
-    for (int c = 0; c < 6; ++c) t[c] = spec[c * s + idx];
+    for (int c = 0; c < 6; ++c) t[c] = spec[c * s + at];
     double er[6] = {0, 0, 0, 0, 0, 0}, ei[6] = {0, 0, 0, 0, 0, 0};
     if ((n1 || n2 || n3) && nonzero >= 2) {
         // -C0^-1 : t; normal strains (t_i - lam0 / (3 lam0 + 2 mu0) tr t) / (2 mu0),
@@ -172,9 +178,51 @@ __global__ void gamma_kernel(hipfftDoubleComplex *spec, MsField f, double lam0, 
         gamma_add(freq(kx, f.nx), freq(ky, f.ny), freq(kz, f.nz), t, c1, c2, er, ei);
     }
     for (int c = 0; c < 6; ++c) {
-        spec[c * s + idx].x = er[c];
-        spec[c * s + idx].y = ei[c];
+        spec[c * s + at].x = er[c];
+        spec[c * s + at].y = ei[c];
     }
+}
+
+// In-plane transforms of 128 x 128 planes (slab_fft.hpp), one work-group
+// per compute unit looping over the 6 nz planes (component-major real
+// fields, plane-major spectra: plane (c, z) at spec + (6 z + c) 128 * 65).
+__global__ __launch_bounds__(slab::kThreads) void xy_forward_kernel(const double *tau,
+                                                                    slab::cd *spec, int nz) {
+    __shared__ slab::cd L[slab::R * slab::LD];
+    __shared__ slab::cd tw[slab::N];
+    slab::init_twiddles(tw);
+    __syncthreads();
+    const int64_t plane = (int64_t)slab::N * slab::N, P = (int64_t)slab::N * slab::NH;
+    for (int p = blockIdx.x; p < 6 * nz; p += gridDim.x) {
+        const int c = p / nz, z = p - c * nz;
+        slab::forward_plane(tau + p * plane, spec + ((int64_t)z * 6 + c) * P, L, tw);
+    }
+}
+
+// The inverse in-plane transforms followed by the strain update
+// eps <- raw / n with the per-block partial sums of the tensor-norm square
+// of the change (partial[blockIdx.x], fixed order).
+__global__ __launch_bounds__(slab::kThreads) void xy_inverse_update_kernel(
+    const slab::cd *spec, double *eps, int nz, double inv_n, double *partial) {
+    __shared__ slab::cd L[slab::R * slab::LD];
+    __shared__ slab::cd tw[slab::N];
+    __shared__ double red[slab::kThreads];
+    slab::init_twiddles(tw);
+    __syncthreads();
+    const int64_t plane = (int64_t)slab::N * slab::N, P = (int64_t)slab::N * slab::NH;
+    double acc = 0.0;
+    for (int p = blockIdx.x; p < 6 * nz; p += gridDim.x) {
+        const int c = p / nz, z = p - c * nz;
+        slab::inverse_plane_update(spec + ((int64_t)z * 6 + c) * P, eps + p * plane, inv_n,
+                                   c < 3 ? 1.0 : 0.5, acc, L, tw);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = slab::kThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
 // eps' = raw / n; partial sums of the tensor norm of eps' - eps per block;
@@ -387,6 +435,11 @@ struct automat_ms {
     double lam0, mu0;
     double E_prev[6];
     hipfftHandle fwd, inv;
+    // grids with nx = ny = 128: in-plane transforms by the slab kernels and
+    // batched transforms along z (plane-major spectrum) by zfft
+    bool slab;
+    int slab_grid;
+    hipfftHandle zfft;
     double *sig;   // [6][n] stress / polarization / raw inverse FFT output
     double *dlt;   // [6][n] increments a_{n+1} - a_n of the last sweep: the next
                    // sweep's Newton solves start there (warm start)
@@ -469,6 +522,20 @@ extern "C" int32_t automat_ms_create(int32_t nx, int32_t ny, int32_t nz,
                               HIPFFT_D2Z, 6) == HIPFFT_SUCCESS;
     ok = ok && hipfftPlanMany(&m->inv, 3, dims, dims_c, 1, (int)m->f.nh, dims, 1, (int)m->f.n,
                               HIPFFT_Z2D, 6) == HIPFFT_SUCCESS;
+    m->slab = nx == slab::N && ny == slab::N;
+    if (ok && m->slab) {
+        const int planes = (int)(ny * (nx / 2 + 1)) * 6;  // columns along z, unit distance
+        int len[1] = {nz};
+        int cus = 0, dev = 0;
+        ok = hipGetDevice(&dev) == hipSuccess &&
+             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+             cus > 0;
+        const int work = 6 * nz;
+        m->slab_grid = work < cus ? work : cus;
+        if (m->slab_grid > kRedBlocks) m->slab_grid = kRedBlocks;
+        ok = ok && hipfftPlanMany(&m->zfft, 1, len, len, planes, 1, len, planes, 1, HIPFFT_Z2Z,
+                                  planes) == HIPFFT_SUCCESS;
+    }
     if (!ok) {
         automat_ms_destroy(m);
         return AUTOMAT_ENOMEM;
@@ -481,6 +548,7 @@ extern "C" int32_t automat_ms_destroy(automat_ms *m) {
     if (!m) return AUTOMAT_OK;
     if (m->fwd) (void)hipfftDestroy(m->fwd);
     if (m->inv) (void)hipfftDestroy(m->inv);
+    if (m->zfft) (void)hipfftDestroy(m->zfft);
     if (m->sig) (void)hipFree(m->sig);
     if (m->dlt) (void)hipFree(m->dlt);
     if (m->spec) (void)hipFree(m->spec);
@@ -577,7 +645,8 @@ static int32_t ms_step_impl(automat_ms *m, const MsWork &w, const uint8_t *phase
     const int64_t n = m->f.n;
     const int tb = 256;
     const int gb = (int)((n + tb - 1) / tb);
-    if (hipfftSetStream(m->fwd, s) != HIPFFT_SUCCESS || hipfftSetStream(m->inv, s) != HIPFFT_SUCCESS)
+    if (hipfftSetStream(m->fwd, s) != HIPFFT_SUCCESS || hipfftSetStream(m->inv, s) != HIPFFT_SUCCESS ||
+        (m->slab && hipfftSetStream(m->zfft, s) != HIPFFT_SUCCESS))
         return AUTOMAT_EHIP;
     hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, s, w.fails);
     MacroBC bc;
@@ -619,13 +688,31 @@ static int32_t ms_step_impl(automat_ms *m, const MsWork &w, const uint8_t *phase
                                 m->opts.newton_max_iter, m->lam0, m->mu0, w.sig, warm(m),
                                 w.fails, stream);
         if (rc) return rc;
-        if (hipfftExecD2Z(m->fwd, w.sig, w.spec) != HIPFFT_SUCCESS) return AUTOMAT_EHIP;
-        hipLaunchKernelGGL(gamma_kernel, dim3(nhb), dim3(tb), 0, s, w.spec, m->f, m->lam0,
-                           m->mu0, bc);
-        if (hipfftExecZ2D(m->inv, w.spec, w.sig) != HIPFFT_SUCCESS) return AUTOMAT_EHIP;
-        hipLaunchKernelGGL(update_kernel, dim3(rb), dim3(kRedBlock), 0, s, eps, w.sig, n,
-                           w.partial);
-        hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedBlock), 0, s, w.partial, rb, w.scal);
+        if (m->slab) {
+            const int64_t P = (int64_t)m->f.ny * (m->f.nx / 2 + 1);
+            slab::cd *sp = reinterpret_cast<slab::cd *>(w.spec);
+            hipLaunchKernelGGL(xy_forward_kernel, dim3(m->slab_grid), dim3(slab::kThreads), 0, s,
+                               w.sig, sp, m->f.nz);
+            if (hipfftExecZ2Z(m->zfft, w.spec, w.spec, HIPFFT_FORWARD) != HIPFFT_SUCCESS)
+                return AUTOMAT_EHIP;
+            hipLaunchKernelGGL(gamma_kernel, dim3(nhb), dim3(tb), 0, s, w.spec, m->f, m->lam0,
+                               m->mu0, bc, P, 6 * P);
+            if (hipfftExecZ2Z(m->zfft, w.spec, w.spec, HIPFFT_BACKWARD) != HIPFFT_SUCCESS)
+                return AUTOMAT_EHIP;
+            hipLaunchKernelGGL(xy_inverse_update_kernel, dim3(m->slab_grid), dim3(slab::kThreads),
+                               0, s, sp, eps, m->f.nz, 1.0 / (double)n, w.partial);
+            hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedBlock), 0, s, w.partial,
+                               m->slab_grid, w.scal);
+        } else {
+            if (hipfftExecD2Z(m->fwd, w.sig, w.spec) != HIPFFT_SUCCESS) return AUTOMAT_EHIP;
+            hipLaunchKernelGGL(gamma_kernel, dim3(nhb), dim3(tb), 0, s, w.spec, m->f, m->lam0,
+                               m->mu0, bc, m->f.nh, (int64_t)m->f.ny * (m->f.nx / 2 + 1));
+            if (hipfftExecZ2D(m->inv, w.spec, w.sig) != HIPFFT_SUCCESS) return AUTOMAT_EHIP;
+            hipLaunchKernelGGL(update_kernel, dim3(rb), dim3(kRedBlock), 0, s, eps, w.sig, n,
+                               w.partial);
+            hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedBlock), 0, s, w.partial, rb,
+                               w.scal);
+        }
         if (!m->opts.fixed_iter || it == m->opts.max_iter) {
             rc = read_scalars(m, w.scal, 14, s);
             if (rc) return rc;
@@ -768,7 +855,7 @@ static int32_t ms_gamma(automat_ms *m, const double *x, hipStream_t s) {
         return AUTOMAT_EHIP;
     if (hipfftExecD2Z(m->fwd, m->sig, m->spec) != HIPFFT_SUCCESS) return AUTOMAT_EHIP;
     hipLaunchKernelGGL(gamma_kernel, dim3(nhb), dim3(tb), 0, s, m->spec, m->f, m->lam0, m->mu0,
-                       bc);
+                       bc, m->f.nh, (int64_t)m->f.ny * (m->f.nx / 2 + 1));
     if (hipfftExecZ2D(m->inv, m->spec, m->sig) != HIPFFT_SUCCESS) return AUTOMAT_EHIP;
     return AUTOMAT_OK;
 }
