@@ -124,40 +124,28 @@ __device__ __forceinline__ void gamma_add(double q1, double q2, double q3,
     }
 }
 
-// eps^ = -Gamma0 : tau^ on the half spectrum (in place); eps^(0) = E * n
-// with E from the macroscopic conditions (above).
-// Value c of frequency (kx, ky, kz) sits at spec[c * cs + kz * zs + ky * nxh
-// + kx]: cs = nh, zs = ny * nxh for component-major spectra (the 3-D
-// transforms), cs = ny * nxh, zs = 6 cs for plane-major ones (the slab
-// transforms).
-__global__ void gamma_kernel(hipfftDoubleComplex *spec, MsField f, double lam0, double mu0,
-                             MacroBC bc, int64_t cs, int64_t zs) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= f.nh) return;
-    const int nxh = f.nx / 2 + 1;
-    const int kx = (int)(idx % nxh);
-    const int ky = (int)((idx / nxh) % f.ny);
-    const int kz = (int)(idx / ((int64_t)nxh * f.ny));
-    const int64_t s = cs;
-    const int64_t at = (int64_t)kz * zs + (int64_t)ky * nxh + kx;
-    if (kx == 0 && ky == 0 && kz == 0) {
-        const double nn = (double)f.n;
-        double r[6], E[6];
-        for (int c = 0; c < 6; ++c) r[c] = bc.S[c] - spec[c * s].x / nn;
-        mixed_solve(lam0, mu0, bc.mask, bc.E, r, E);
-        for (int c = 0; c < 6; ++c) {
-            spec[c * s].x = E[c] * nn;
-            spec[c * s].y = 0.0;
-            if (bc.Eout) bc.Eout[c] = E[c];
-        }
-        return;
+// The zero frequency: t holds tau^(0) = n mean(tau) in, E n out (the
+// macroscopic strain of the update, also written to bc.Eout).
+__device__ __forceinline__ void gamma_zero(hipfftDoubleComplex *t, const MsField &f, double lam0,
+                                           double mu0, const MacroBC &bc) {
+    const double nn = (double)f.n;
+    double r[6], E[6];
+    for (int c = 0; c < 6; ++c) r[c] = bc.S[c] - t[c].x / nn;
+    mixed_solve(lam0, mu0, bc.mask, bc.E, r, E);
+    for (int c = 0; c < 6; ++c) {
+        t[c].x = E[c] * nn;
+        t[c].y = 0.0;
+        if (bc.Eout) bc.Eout[c] = E[c];
     }
+}
+
+// eps^ = -Gamma0 : tau^ at the non-zero frequency (kx, ky, kz), in place
+__device__ __forceinline__ void gamma_point(hipfftDoubleComplex *t, const MsField &f, int kx,
+                                            int ky, int kz, double lam0, double mu0) {
     const bool n1 = (f.nx % 2 == 0) && kx == f.nx / 2;
     const bool n2 = (f.ny % 2 == 0) && ky == f.ny / 2;
     const bool n3 = (f.nz % 2 == 0) && kz == f.nz / 2;
     const int nonzero = (kx != 0) + (ky != 0) + (kz != 0);
-    hipfftDoubleComplex t[6];
-    for (int c = 0; c < 6; ++c) t[c] = spec[c * s + at];
     double er[6] = {0, 0, 0, 0, 0, 0}, ei[6] = {0, 0, 0, 0, 0, 0};
     if ((n1 || n2 || n3) && nonzero >= 2) {
         // -C0^-1 : t; normal strains (t_i - lam0 / (3 lam0 + 2 mu0) tr t) / (2 mu0),
@@ -178,8 +166,131 @@ __global__ void gamma_kernel(hipfftDoubleComplex *spec, MsField f, double lam0, 
         gamma_add(freq(kx, f.nx), freq(ky, f.ny), freq(kz, f.nz), t, c1, c2, er, ei);
     }
     for (int c = 0; c < 6; ++c) {
-        spec[c * s + at].x = er[c];
-        spec[c * s + at].y = ei[c];
+        t[c].x = er[c];
+        t[c].y = ei[c];
+    }
+}
+
+// eps^ = -Gamma0 : tau^ on the half spectrum (in place); eps^(0) = E * n
+// with E from the macroscopic conditions (above).
+// Value c of frequency (kx, ky, kz) sits at spec[c * cs + kz * zs + ky * nxh
+// + kx]: cs = nh, zs = ny * nxh for component-major spectra (the 3-D
+// transforms), cs = ny * nxh, zs = 6 cs for plane-major ones (the slab
+// transforms).
+__global__ void gamma_kernel(hipfftDoubleComplex *spec, MsField f, double lam0, double mu0,
+                             MacroBC bc, int64_t cs, int64_t zs) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= f.nh) return;
+    const int nxh = f.nx / 2 + 1;
+    const int kx = (int)(idx % nxh);
+    const int ky = (int)((idx / nxh) % f.ny);
+    const int kz = (int)(idx / ((int64_t)nxh * f.ny));
+    const int64_t at = (int64_t)kz * zs + (int64_t)ky * nxh + kx;
+    hipfftDoubleComplex t[6];
+    for (int c = 0; c < 6; ++c) t[c] = spec[c * cs + at];
+    if (kx == 0 && ky == 0 && kz == 0)
+        gamma_zero(t, f, lam0, mu0, bc);
+    else
+        gamma_point(t, f, kx, ky, kz, lam0, mu0);
+    for (int c = 0; c < 6; ++c) spec[c * cs + at] = t[c];
+}
+
+// The transforms along z (length 128) with Gamma0 between them, for the
+// plane-major spectra of 128^3 grids: a work-group takes kZR = 4
+// consecutive in-plane frequencies r = ky * 65 + kx with all six
+// components (24 columns of 128 values, 8 lanes each: the radix-16 and
+// radix-8 passes of slab_fft.hpp), keeps them in LDS between the forward
+// transform, the Green operator (the six components of one frequency
+// together) and the inverse transform, and writes them back in place.
+// Neighbouring work-groups share 128-byte lines; blocks are dispatched to
+// the eight XCDs in turn, so block b takes group (b % 8) G / 8 + b / 8 and
+// each XCD walks a contiguous range of groups.
+constexpr int kZR = 4;
+constexpr int kZThreads = 6 * kZR * 8;
+constexpr int kZLD = slab::N + 1;
+__global__ __launch_bounds__(kZThreads) void z_gamma_kernel(slab::cd *spec, MsField f,
+                                                            double lam0, double mu0, MacroBC bc) {
+    using slab::cd;
+    __shared__ cd X[6 * kZR * kZLD];
+    __shared__ cd tw[slab::N];
+    slab::init_twiddles(tw);
+    const int G = (int)gridDim.x;
+    const int b = (int)blockIdx.x;
+    const int grp = G % 8 == 0 ? (b % 8) * (G / 8) + b / 8 : b;
+    const int64_t P = (int64_t)slab::N * slab::NH;
+    const int r0 = grp * kZR;
+    const int t = threadIdx.x;
+    const int rr = t & (kZR - 1), l = (t / kZR) & 7, c = t / (kZR * 8);
+    const int col = c * kZR + rr;
+    cd *base = spec + (int64_t)c * P + r0 + rr;  // + z * 6 P
+    __syncthreads();
+    {
+        cd v[16];
+#pragma unroll
+        for (int n1 = 0; n1 < 16; ++n1) v[n1] = base[(int64_t)(8 * n1 + l) * 6 * P];
+        slab::pass16<false>(v, l, tw);
+#pragma unroll
+        for (int k1 = 0; k1 < 16; ++k1) X[col * kZLD + 8 * k1 + l] = v[k1];
+    }
+    __syncthreads();
+    {
+        cd a[8], bb[8];
+#pragma unroll
+        for (int n2 = 0; n2 < 8; ++n2) {
+            a[n2] = X[col * kZLD + 8 * l + n2];
+            bb[n2] = X[col * kZLD + 8 * (l + 8) + n2];
+        }
+        slab::dft8<false>(a);
+        slab::dft8<false>(bb);
+        __syncthreads();
+#pragma unroll
+        for (int k2 = 0; k2 < 8; ++k2) {
+            X[col * kZLD + l + 16 * k2] = a[k2];
+            X[col * kZLD + l + 8 + 16 * k2] = bb[k2];
+        }
+    }
+    __syncthreads();
+    for (int q = t; q < slab::N * kZR; q += kZThreads) {
+        const int kz = q / kZR, qr = q - kz * kZR;
+        const int r = r0 + qr;
+        const int ky = r / slab::NH, kx = r - ky * slab::NH;
+        hipfftDoubleComplex v6[6];
+        for (int cc = 0; cc < 6; ++cc) {
+            const cd x = X[(cc * kZR + qr) * kZLD + kz];
+            v6[cc].x = x.re;
+            v6[cc].y = x.im;
+        }
+        if (r == 0 && kz == 0)
+            gamma_zero(v6, f, lam0, mu0, bc);
+        else
+            gamma_point(v6, f, kx, ky, kz, lam0, mu0);
+        for (int cc = 0; cc < 6; ++cc) X[(cc * kZR + qr) * kZLD + kz] = {v6[cc].x, v6[cc].y};
+    }
+    __syncthreads();
+    {
+        cd v[16];
+#pragma unroll
+        for (int n1 = 0; n1 < 16; ++n1) v[n1] = X[col * kZLD + 8 * n1 + l];
+        slab::pass16<true>(v, l, tw);
+        __syncthreads();
+#pragma unroll
+        for (int k1 = 0; k1 < 16; ++k1) X[col * kZLD + 8 * k1 + l] = v[k1];
+    }
+    __syncthreads();
+    {
+        cd a[8], bb[8];
+#pragma unroll
+        for (int n2 = 0; n2 < 8; ++n2) {
+            a[n2] = X[col * kZLD + 8 * l + n2];
+            bb[n2] = X[col * kZLD + 8 * (l + 8) + n2];
+        }
+        slab::dft8<true>(a);
+        slab::dft8<true>(bb);
+#pragma unroll
+        for (int k2 = 0; k2 < 8; ++k2) {
+            base[(int64_t)(l + 16 * k2) * 6 * P] = a[k2];
+            base[(int64_t)(l + 8 + 16 * k2) * 6 * P] = bb[k2];
+        }
     }
 }
 
@@ -435,9 +546,10 @@ struct automat_ms {
     double lam0, mu0;
     double E_prev[6];
     hipfftHandle fwd, inv;
-    // grids with nx = ny = 128: in-plane transforms by the slab kernels and
-    // batched transforms along z (plane-major spectrum) by zfft
-    bool slab;
+    // grids with nx = ny = 128: in-plane transforms by the slab kernels,
+    // the transforms along z (plane-major spectrum) with Gamma0 between them
+    // by z_gamma_kernel where nz = 128 too (zfused), else by zfft
+    bool slab, zfused;
     int slab_grid;
     hipfftHandle zfft;
     double *sig;   // [6][n] stress / polarization / raw inverse FFT output
@@ -533,8 +645,9 @@ extern "C" int32_t automat_ms_create(int32_t nx, int32_t ny, int32_t nz,
         const int work = 6 * nz;
         m->slab_grid = work < cus ? work : cus;
         if (m->slab_grid > kRedBlocks) m->slab_grid = kRedBlocks;
-        ok = ok && hipfftPlanMany(&m->zfft, 1, len, len, planes, 1, len, planes, 1, HIPFFT_Z2Z,
-                                  planes) == HIPFFT_SUCCESS;
+        m->zfused = nz == slab::N;
+        ok = ok && (m->zfused || hipfftPlanMany(&m->zfft, 1, len, len, planes, 1, len, planes, 1,
+                                                HIPFFT_Z2Z, planes) == HIPFFT_SUCCESS);
     }
     if (!ok) {
         automat_ms_destroy(m);
@@ -646,7 +759,7 @@ static int32_t ms_step_impl(automat_ms *m, const MsWork &w, const uint8_t *phase
     const int tb = 256;
     const int gb = (int)((n + tb - 1) / tb);
     if (hipfftSetStream(m->fwd, s) != HIPFFT_SUCCESS || hipfftSetStream(m->inv, s) != HIPFFT_SUCCESS ||
-        (m->slab && hipfftSetStream(m->zfft, s) != HIPFFT_SUCCESS))
+        (m->zfft && hipfftSetStream(m->zfft, s) != HIPFFT_SUCCESS))
         return AUTOMAT_EHIP;
     hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, s, w.fails);
     MacroBC bc;
@@ -693,12 +806,17 @@ static int32_t ms_step_impl(automat_ms *m, const MsWork &w, const uint8_t *phase
             slab::cd *sp = reinterpret_cast<slab::cd *>(w.spec);
             hipLaunchKernelGGL(xy_forward_kernel, dim3(m->slab_grid), dim3(slab::kThreads), 0, s,
                                w.sig, sp, m->f.nz);
-            if (hipfftExecZ2Z(m->zfft, w.spec, w.spec, HIPFFT_FORWARD) != HIPFFT_SUCCESS)
-                return AUTOMAT_EHIP;
-            hipLaunchKernelGGL(gamma_kernel, dim3(nhb), dim3(tb), 0, s, w.spec, m->f, m->lam0,
-                               m->mu0, bc, P, 6 * P);
-            if (hipfftExecZ2Z(m->zfft, w.spec, w.spec, HIPFFT_BACKWARD) != HIPFFT_SUCCESS)
-                return AUTOMAT_EHIP;
+            if (m->zfused) {
+                hipLaunchKernelGGL(z_gamma_kernel, dim3((int)(P / kZR)), dim3(kZThreads), 0, s, sp,
+                                   m->f, m->lam0, m->mu0, bc);
+            } else {
+                if (hipfftExecZ2Z(m->zfft, w.spec, w.spec, HIPFFT_FORWARD) != HIPFFT_SUCCESS)
+                    return AUTOMAT_EHIP;
+                hipLaunchKernelGGL(gamma_kernel, dim3(nhb), dim3(tb), 0, s, w.spec, m->f, m->lam0,
+                                   m->mu0, bc, P, 6 * P);
+                if (hipfftExecZ2Z(m->zfft, w.spec, w.spec, HIPFFT_BACKWARD) != HIPFFT_SUCCESS)
+                    return AUTOMAT_EHIP;
+            }
             hipLaunchKernelGGL(xy_inverse_update_kernel, dim3(m->slab_grid), dim3(slab::kThreads),
                                0, s, sp, eps, m->f.nz, 1.0 / (double)n, w.partial);
             hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedBlock), 0, s, w.partial,
