@@ -19,6 +19,10 @@ what the GPU tests compare with:
   stiffness adjusted from the tangent field every step, 10 fixed-point
   iterations per step; the same quantities plus the macroscopic strain
   reached and the reference Lame constants;
+* ``ms_mmc128_mixed_lockstep.npz``: the same test on a 128^3 synthetic
+  metal-matrix composite (seed 5), 8 fixed-point iterations per step (the
+  grid size on which the basic scheme's transforms run in-plane and along z
+  in kernels of their own);
 * ``ms_spheres64_derivatives.json``: the 64^3 sphere microstructure (seed
   3), five load steps of the same strain path converged to 1e-12; the
   derivative of the last mean stress with respect to the last macroscopic
@@ -26,8 +30,8 @@ what the GPU tests compare with:
   history, from the oracle's linearized scheme (forward derivatives).
 
 Run from the repository root: ``python tests/golden/make_ms_golden.py``
-(about 20 minutes on 8 cores; ``--only NAME`` runs one of lockstep128,
-mixed150, derivatives64).
+(about 25 minutes on 8 cores; ``--only NAME`` runs one of lockstep128,
+mixed150, mixed128, derivatives64).
 """
 from __future__ import annotations
 
@@ -93,10 +97,9 @@ def lockstep128():
     np.savez(os.path.join(HERE, "ms_spheres128_lockstep.npz"), **out)
 
 
-def mixed150():
-    N, iters = 150, 10
+def mixed150(N=150, iters=10, seed=4, name="ms_mmc150_mixed_lockstep.npz"):
     shape = (N, N, N)
-    phase = inputs.mmc_phase(N, seed=4)
+    phase = inputs.mmc_phase(N, seed=seed)
     ph = inputs.paper_phases()
     h, path = inputs.tension_compression_path(8)
     n = N ** 3
@@ -116,9 +119,13 @@ def mixed150():
         out[f"step{k}_reference"] = np.array([r["lam0"], r["mu0"]])
         _field_stats(out, f"step{k}_", r, idx)
         eps, a, prev, lam0, mu0 = r["eps"], r["a"], r["E"], r["lam0"], r["mu0"]
-        _log(f"mixed150 step {k}: {time.perf_counter() - t0:.1f} s, residual "
+        _log(f"mixed{N} step {k}: {time.perf_counter() - t0:.1f} s, residual "
              f"{r['residual']:.3e}, E {r['E']}, reference {r['lam0']:.1f} {r['mu0']:.1f}")
-    np.savez(os.path.join(HERE, "ms_mmc150_mixed_lockstep.npz"), **out)
+    np.savez(os.path.join(HERE, name), **out)
+
+
+def mixed128():
+    mixed150(N=128, iters=8, seed=5, name="ms_mmc128_mixed_lockstep.npz")
 
 
 def derivatives64():
@@ -176,9 +183,10 @@ def derivatives64():
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--only", choices=["lockstep128", "mixed150", "derivatives64"])
+    ap.add_argument("--only", choices=["lockstep128", "mixed150", "mixed128", "derivatives64"])
     args = ap.parse_args()
-    jobs = dict(lockstep128=lockstep128, mixed150=mixed150, derivatives64=derivatives64)
+    jobs = dict(lockstep128=lockstep128, mixed150=mixed150, mixed128=mixed128,
+                derivatives64=derivatives64)
     for name, fn in jobs.items():
         if args.only in (None, name):
             fn()

@@ -9,6 +9,9 @@ agree to rounding.
   the tension-compression cycle under uniaxial mixed conditions with the
   reference stiffness adjusted from the tangent field every step (hipFFT
   plans of length 150 = 2 3 5^2), 10 iterations each;
+* the same on a 128^3 composite, 8 iterations each (the in-plane slab
+  transforms and the fused z transform with the Green operator, whose
+  zero frequency then carries the mixed conditions);
 * 64^3 spheres, five converged steps: the reverse steps' derivatives of the
   last mean stress against the oracle's linearized scheme (forward
   derivatives, an independent route to the same numbers).
@@ -81,15 +84,16 @@ def test_spheres128_lockstep_against_oracle():
     ms.close()
 
 
-def test_mmc150_mixed_reference_update_lockstep_against_oracle():
+@pytest.mark.parametrize("N,seed,name", [(150, 4, "ms_mmc150_mixed_lockstep.npz"),
+                                          (128, 5, "ms_mmc128_mixed_lockstep.npz")])
+def test_mmc_mixed_reference_update_lockstep_against_oracle(N, seed, name):
     from paper_2006_04391_amd import api
     _need_gpu()
-    ref = np.load(os.path.join(GOLDEN, "ms_mmc150_mixed_lockstep.npz"))
-    N = 150
+    ref = np.load(os.path.join(GOLDEN, name))
     n = N ** 3
     it = int(ref["iterations"])
     h = float(ref["h"])
-    phase = torch.from_numpy(inputs.mmc_phase(N, seed=4)).cuda()
+    phase = torch.from_numpy(inputs.mmc_phase(N, seed=seed)).cuda()
     ms = api.MS((N, N, N), inputs.paper_phases(), tol=1e-30, max_iter=it, fixed_iter=True,
                 ref_update=True)
     eps = torch.zeros((6, n), dtype=torch.float64, device="cuda")
@@ -117,7 +121,7 @@ def test_mmc150_mixed_reference_update_lockstep_against_oracle():
 
 
 def test_spheres64_derivatives_against_oracle_linearized_scheme():
-    """configs' differentiation case: d<sigma_5>/dE_5 (6 x 6) and
+    """The 64^3 differentiation workload: d<sigma_5>/dE_5 (6 x 6) and
     d<sigma_5>/d(E, nu, sigma0, n) of the matrix over the five-step history
     from the GPU's reverse steps, against the oracle's forward derivatives
     (linearized Lippmann-Schwinger solves on the oracle's tangent field).
