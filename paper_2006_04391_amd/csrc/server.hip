@@ -7,16 +7,22 @@
 // device block (phase ids, internal variables, stress: 97 B per point, plus
 // the phase tables) fits in the arena (first-fit, coalescing). Every round
 // builds one batch with the next load step of admitted requests (a ragged
-// table of segments) and launches one kernel over all of them; while it
-// runs, requests that arrived meanwhile are admitted and their inputs
-// uploaded on the second stream (their first batch waits for an event). A
+// table of segments) and launches one kernel over all of them. Two rounds
+// are in flight: the next batch is queued behind the running one (a
+// request's next load step may follow its previous one, stream order keeps
+// them apart) before the scheduler waits for the older one, so the device
+// does not idle while the host retires a round and builds the next.
+// Requests that arrived meanwhile are admitted and their inputs uploaded on
+// a second stream (their first batch waits for an event); the results of
+// finished requests are copied on a third stream once their last batch is
+// done, without waiting for the batch behind it. A
 // batch takes the requests with the least remaining work first (points
 // times load steps left) up to an optional point cap, with aging so that no
 // request waits more than a few batches: small and nearly finished requests
 // are not held behind large ones. Finished requests return their block at
 // once. In sequential mode only one
-// request is admitted at a time (one launch and one wait per load step),
-// which is the per-request baseline.
+// request is admitted at a time (one launch per load step, its load steps
+// queued two deep like the batches), which is the per-request baseline.
 //
 // Device side: the batch kernel strides a resident grid over the 256-point
 // tiles of all segments. A tile belongs to one segment: the block finds it
@@ -357,7 +363,8 @@ struct Req {
     Model::Phase *d_raw = nullptr;
     unsigned long long *d_nonconv = nullptr;
     hipEvent_t ready = nullptr;  // uploads and table build done
-    int32_t steps_done = 0;
+    int32_t steps_done = 0;      // load steps of retired batches
+    int32_t steps_launched = 0;  // load steps of launched batches
     int64_t last_round = 0;      // round of the last batch that took a step of it
     double t_arrival = 0, t_admit = 0, t_done = 0;
     int32_t status = 0;
@@ -383,12 +390,15 @@ struct automat_server {
     bool stop = false;
     uint64_t next_id = 1;
     std::chrono::steady_clock::time_point t0;
-    hipStream_t stream = nullptr;  // batch kernels and result copies
+    hipStream_t stream = nullptr;  // batch kernels
     hipStream_t up = nullptr;      // admissions: uploads and table builds
+    hipStream_t down = nullptr;    // result copies of finished requests
     char *arena_base = nullptr;
     Arena arena;
-    Segment *d_segs = nullptr, *h_segs = nullptr;
-    int seg_cap = 0;
+    // per round slot (two rounds in flight): segment tables, timing events
+    Segment *d_segs[2] = {nullptr, nullptr}, *h_segs[2] = {nullptr, nullptr};
+    int seg_cap[2] = {0, 0};
+    hipEvent_t ev_start[2] = {nullptr, nullptr}, ev_end[2] = {nullptr, nullptr};
     int64_t round = 0;  // batches built so far
     // statistics
     int64_t launches = 0, updates = 0;
@@ -410,19 +420,21 @@ static void take_admissible(automat_server *s, std::vector<Req *> &fresh) {
     }
 }
 
-static void finish(automat_server *s, Req *q, int32_t status) {
+// Retire a request: copy its results (status OK: after the event `after`,
+// which marks its last batch, on the copy stream), return its block.
+static void finish(automat_server *s, Req *q, int32_t status, hipEvent_t after = nullptr) {
     unsigned long long nc = 0;
     if (status == AUTOMAT_OK) {
-        bool ok = true;
+        bool ok = !after || hipStreamWaitEvent(s->down, after, 0) == hipSuccess;
         if (q->r.sigma_host)
             ok = ok && hipMemcpyAsync(q->r.sigma_host, q->d_sigma, (size_t)q->r.n * 6 * sizeof(double),
-                                      hipMemcpyDeviceToHost, s->stream) == hipSuccess;
+                                      hipMemcpyDeviceToHost, s->down) == hipSuccess;
         if (q->r.a_host)
             ok = ok && hipMemcpyAsync(q->r.a_host, q->d_a, (size_t)q->r.n * 6 * sizeof(double),
-                                      hipMemcpyDeviceToHost, s->stream) == hipSuccess;
-        ok = ok && hipMemcpyAsync(&nc, q->d_nonconv, sizeof nc, hipMemcpyDeviceToHost, s->stream) ==
+                                      hipMemcpyDeviceToHost, s->down) == hipSuccess;
+        ok = ok && hipMemcpyAsync(&nc, q->d_nonconv, sizeof nc, hipMemcpyDeviceToHost, s->down) ==
                        hipSuccess;
-        ok = ok && hipStreamSynchronize(s->stream) == hipSuccess;
+        ok = ok && hipStreamSynchronize(s->down) == hipSuccess;
         if (!ok) status = AUTOMAT_EHIP;
     } else if (q->ready) {
         // the block may still be written by an upload: let it drain first
@@ -484,6 +496,11 @@ static int32_t start_upload(automat_server *s, Req *q) {
 }
 
 static void admit(automat_server *s, std::vector<Req *> &fresh) {
+    // the smallest first: their inputs arrive first and the first batches
+    // (least remaining work first) need them
+    std::stable_sort(fresh.begin(), fresh.end(), [](const Req *a, const Req *b) {
+        return a->r.n * (int64_t)a->r.steps < b->r.n * (int64_t)b->r.steps;
+    });
     for (Req *q : fresh) {
         const int32_t rc = start_upload(s, q);
         if (rc != AUTOMAT_OK) finish(s, q, rc);
@@ -494,14 +511,165 @@ static void admit(automat_server *s, std::vector<Req *> &fresh) {
 // batches a request may be left out of before it goes first
 constexpr int64_t kAging = 16;
 
+// a launched batch that is not retired yet
+struct Round {
+    std::vector<Req *> batch;
+    int slot = 0;
+    bool ok = true;
+};
+
+static bool ensure_segs(automat_server *s, int slot, int need) {
+    if (need <= s->seg_cap[slot]) return true;
+    if (s->d_segs[slot]) (void)hipFree(s->d_segs[slot]);
+    if (s->h_segs[slot]) (void)hipHostFree(s->h_segs[slot]);
+    const int cap = std::min<int>(kMaxSegs, std::max<int>(need, 2 * s->seg_cap[slot]));
+    if (hipMalloc(&s->d_segs[slot], seg_bytes(cap)) != hipSuccess ||
+        hipHostMalloc(&s->h_segs[slot], seg_bytes(cap), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        s->seg_cap[slot] = 0;
+        s->d_segs[slot] = nullptr;
+        s->h_segs[slot] = nullptr;
+        return false;
+    }
+    s->seg_cap[slot] = cap;
+    return true;
+}
+
+// Build the next batch from the active requests with load steps left to
+// launch. Latency-aware order: the least remaining work (points x steps not
+// launched) first, so that small and nearly finished requests are not held
+// behind large ones; a request left out of kAging consecutive batches goes
+// first. The point cap admits at least one request.
+static void build_batch(automat_server *s, std::vector<Req *> &order, std::vector<Req *> &batch) {
+    batch.clear();
+    std::lock_guard<std::mutex> lock(s->mu);
+    order.clear();
+    // requests whose inputs are still being uploaded wait for a later batch
+    // while others are ready (a batch would otherwise stall on their upload)
+    for (Req *q : s->active)
+        if (q->steps_launched < q->r.steps &&
+            (q->steps_launched > 0 || hipEventQuery(q->ready) == hipSuccess))
+            order.push_back(q);
+    if (order.empty()) {
+        for (Req *q : s->active)
+            if (q->steps_launched < q->r.steps) order.push_back(q);
+    }
+    if (order.empty()) return;
+    const int64_t rnd = ++s->round;
+    auto starved = [&](const Req *q) { return rnd - q->last_round > kAging; };
+    auto remaining = [](const Req *q) { return q->r.n * (int64_t)(q->r.steps - q->steps_launched); };
+    std::stable_sort(order.begin(), order.end(), [&](const Req *a, const Req *b) {
+        if (starved(a) != starved(b)) return starved(a);
+        return remaining(a) < remaining(b);
+    });
+    int64_t pts = 0;
+    for (Req *q : order) {
+        if (batch.size() >= (size_t)kMaxSegs) break;
+        if (!batch.empty() && s->max_batch_points > 0 && pts + q->r.n > s->max_batch_points)
+            continue;
+        batch.push_back(q);
+        pts += q->r.n;
+        q->last_round = rnd;
+    }
+}
+
+// Queue one batch (segment table upload and kernel) on the batch stream
+// between the slot's timing events.
+static bool launch_round(automat_server *s, Round &r) {
+    const int slot = r.slot;
+    if (!ensure_segs(s, slot, (int)r.batch.size())) return false;
+    Segment *hs = s->h_segs[slot];
+    int64_t tiles = 0;
+    bool ok = hipEventRecord(s->ev_start[slot], s->stream) == hipSuccess;
+    for (size_t k = 0; k < r.batch.size(); ++k) {
+        Req *q = r.batch[k];
+        if (q->steps_launched == 0)
+            ok = ok && hipStreamWaitEvent(s->stream, q->ready, 0) == hipSuccess;
+        Segment &g = hs[k];
+        g.phase = q->d_phase;
+        g.a = q->d_a;
+        g.sigma = q->d_sigma;
+        g.tab = q->d_tab;
+        g.nonconv = q->d_nonconv;
+        g.n = q->r.n;
+        g.tile0 = tiles;
+        const int32_t step = q->steps_launched + 1;
+        for (int c = 0; c < 6; ++c) g.E[c] = q->r.E_final[c] * ((double)step / q->r.steps);
+        g.noise = q->r.noise_std;
+        g.h = q->r.h;
+        g.tol = q->r.tol;
+        g.key0 = (uint32_t)q->r.seed;
+        g.key1 = (uint32_t)(q->r.seed >> 32);
+        g.step = (uint32_t)step;
+        g.max_iter = q->r.max_iter;
+        g.n_phases = q->nph;
+        g.reserved = 0;
+        tiles += (q->r.n + kBlock - 1) / kBlock;
+    }
+    const int nseg = (int)r.batch.size();
+    int32_t *h_first = reinterpret_cast<int32_t *>(hs + s->seg_cap[slot]);
+    for (int k = 0; k < nseg; ++k) h_first[k] = (int32_t)hs[k].tile0;
+    h_first[nseg] = (int32_t)tiles;
+    int32_t *d_first = reinterpret_cast<int32_t *>(s->d_segs[slot] + s->seg_cap[slot]);
+    ok = ok && tiles < INT32_MAX &&
+         hipMemcpyAsync(s->d_segs[slot], hs, nseg * sizeof(Segment), hipMemcpyHostToDevice,
+                        s->stream) == hipSuccess &&
+         hipMemcpyAsync(d_first, h_first, (nseg + 1) * sizeof(int32_t), hipMemcpyHostToDevice,
+                        s->stream) == hipSuccess;
+    const int grid = (int)std::min<int64_t>(tiles, (int64_t)s->grid);
+    if (ok) {
+        hipLaunchKernelGGL(serve_batch_kernel, dim3(grid), dim3(kBlock), serve_smem_bytes(),
+                           s->stream, s->d_segs[slot], d_first, nseg, (int32_t)tiles);
+        ok = hipGetLastError() == hipSuccess;
+    }
+    ok = ok && hipEventRecord(s->ev_end[slot], s->stream) == hipSuccess;
+    for (Req *q : r.batch) q->steps_launched += 1;
+    return ok;
+}
+
+// Wait for the oldest round and retire it: its requests have one more load
+// step done; those with all steps done are finished (results copied after
+// the round's end event, not after the round queued behind it).
+static void retire_round(automat_server *s, std::deque<Round> &inflight) {
+    Round r = std::move(inflight.front());
+    inflight.pop_front();
+    bool ok = r.ok && hipEventSynchronize(s->ev_end[r.slot]) == hipSuccess;
+    float ms = 0.0f;
+    if (ok && hipEventElapsedTime(&ms, s->ev_start[r.slot], s->ev_end[r.slot]) == hipSuccess)
+        s->busy_s += 1e-3 * ms;
+    s->launches += 1;
+    if (!ok) {
+        // drain everything queued, then fail every request of every round
+        // in flight once
+        (void)hipStreamSynchronize(s->stream);
+        std::vector<Req *> all(r.batch);
+        for (Round &o : inflight) all.insert(all.end(), o.batch.begin(), o.batch.end());
+        inflight.clear();
+        std::sort(all.begin(), all.end());
+        all.erase(std::unique(all.begin(), all.end()), all.end());
+        for (Req *q : all) finish(s, q, AUTOMAT_EHIP);
+        return;
+    }
+    for (Req *q : r.batch) {
+        q->steps_done += 1;
+        s->updates += q->r.n;
+        if (q->steps_done >= q->r.steps) finish(s, q, AUTOMAT_OK, s->ev_end[r.slot]);
+    }
+}
+
+constexpr int kInFlight = 2;
+
 static void worker_loop(automat_server *s) {
     (void)hipSetDevice(s->device);
-    std::vector<Req *> batch, fresh, order;
+    std::vector<Req *> fresh, order;
+    std::deque<Round> inflight;
     for (;;) {
         {
             std::unique_lock<std::mutex> lock(s->mu);
-            s->cv.wait(lock, [&] { return s->stop || !s->pending.empty() || !s->active.empty(); });
-            if (s->stop && s->active.empty()) {
+            if (inflight.empty())
+                s->cv.wait(lock,
+                           [&] { return s->stop || !s->pending.empty() || !s->active.empty(); });
+            if (s->stop && s->active.empty() && inflight.empty()) {
                 for (Req *q : s->pending) {
                     automat_result res{};
                     res.id = q->id;
@@ -517,105 +685,19 @@ static void worker_loop(automat_server *s) {
             take_admissible(s, fresh);
         }
         admit(s, fresh);
-        // one batch: the next load step of active requests while the point
-        // budget lasts (at least one request). Latency-aware order: the
-        // least remaining work (points x steps left) first, so that small
-        // and nearly finished requests are not held behind large ones; a
-        // request left out of kAging consecutive batches goes first.
-        batch.clear();
-        {
-            std::lock_guard<std::mutex> lock(s->mu);
-            order.assign(s->active.begin(), s->active.end());
-            const int64_t rnd = ++s->round;
-            auto starved = [&](const Req *q) { return rnd - q->last_round > kAging; };
-            auto remaining = [](const Req *q) { return q->r.n * (int64_t)(q->r.steps - q->steps_done); };
-            std::stable_sort(order.begin(), order.end(), [&](const Req *a, const Req *b) {
-                if (starved(a) != starved(b)) return starved(a);
-                return remaining(a) < remaining(b);
-            });
-            int64_t pts = 0;
-            for (Req *q : order) {
-                if (batch.size() >= (size_t)kMaxSegs) break;
-                if (!batch.empty() && s->max_batch_points > 0 && pts + q->r.n > s->max_batch_points)
-                    continue;
-                batch.push_back(q);
-                pts += q->r.n;
-                q->last_round = rnd;
+        bool launched = false;
+        if ((int)inflight.size() < kInFlight) {
+            Round r;
+            build_batch(s, order, r.batch);
+            if (!r.batch.empty()) {
+                r.slot = inflight.empty() ? 0 : 1 - inflight.back().slot;
+                r.ok = launch_round(s, r);
+                inflight.push_back(std::move(r));
+                launched = true;
             }
         }
-        if (batch.empty()) continue;
-        if ((int)batch.size() > s->seg_cap) {
-            if (s->d_segs) (void)hipFree(s->d_segs);
-            if (s->h_segs) (void)hipHostFree(s->h_segs);
-            s->seg_cap = std::min<int>(kMaxSegs, std::max<int>((int)batch.size(), 2 * s->seg_cap));
-            if (hipMalloc(&s->d_segs, seg_bytes(s->seg_cap)) != hipSuccess ||
-                hipHostMalloc(&s->h_segs, seg_bytes(s->seg_cap), hipHostMallocDefault) !=
-                    hipSuccess) {
-                s->seg_cap = 0;
-                s->d_segs = nullptr;
-                s->h_segs = nullptr;
-                for (Req *q : batch) finish(s, q, AUTOMAT_ENOMEM);
-                continue;
-            }
-        }
-        int64_t tiles = 0;
-        bool ok = true;
-        for (size_t k = 0; k < batch.size(); ++k) {
-            Req *q = batch[k];
-            if (q->steps_done == 0)
-                ok = ok && hipStreamWaitEvent(s->stream, q->ready, 0) == hipSuccess;
-            Segment &g = s->h_segs[k];
-            g.phase = q->d_phase;
-            g.a = q->d_a;
-            g.sigma = q->d_sigma;
-            g.tab = q->d_tab;
-            g.nonconv = q->d_nonconv;
-            g.n = q->r.n;
-            g.tile0 = tiles;
-            const int32_t step = q->steps_done + 1;
-            for (int c = 0; c < 6; ++c) g.E[c] = q->r.E_final[c] * ((double)step / q->r.steps);
-            g.noise = q->r.noise_std;
-            g.h = q->r.h;
-            g.tol = q->r.tol;
-            g.key0 = (uint32_t)q->r.seed;
-            g.key1 = (uint32_t)(q->r.seed >> 32);
-            g.step = (uint32_t)step;
-            g.max_iter = q->r.max_iter;
-            g.n_phases = q->nph;
-            g.reserved = 0;
-            tiles += (q->r.n + kBlock - 1) / kBlock;
-        }
-        const int nseg = (int)batch.size();
-        int32_t *h_first = reinterpret_cast<int32_t *>(s->h_segs + s->seg_cap);
-        for (int k = 0; k < nseg; ++k) h_first[k] = (int32_t)s->h_segs[k].tile0;
-        h_first[nseg] = (int32_t)tiles;
-        const double tb = now_s(s->t0);
-        int32_t *d_first = reinterpret_cast<int32_t *>(s->d_segs + s->seg_cap);
-        ok = ok && tiles < INT32_MAX &&
-             hipMemcpyAsync(s->d_segs, s->h_segs, nseg * sizeof(Segment), hipMemcpyHostToDevice,
-                            s->stream) == hipSuccess &&
-             hipMemcpyAsync(d_first, h_first, (nseg + 1) * sizeof(int32_t), hipMemcpyHostToDevice,
-                            s->stream) == hipSuccess;
-        const int grid = (int)std::min<int64_t>(tiles, (int64_t)s->grid);
-        if (ok) {
-            hipLaunchKernelGGL(serve_batch_kernel, dim3(grid), dim3(kBlock), serve_smem_bytes(),
-                               s->stream, s->d_segs, d_first, nseg, (int32_t)tiles);
-            ok = hipGetLastError() == hipSuccess;
-        }
-        // admissions of requests that arrived meanwhile overlap the batch
-        {
-            std::lock_guard<std::mutex> lock(s->mu);
-            take_admissible(s, fresh);
-        }
-        admit(s, fresh);
-        ok = hipStreamSynchronize(s->stream) == hipSuccess && ok;
-        s->busy_s += now_s(s->t0) - tb;
-        s->launches += 1;
-        for (Req *q : batch) {
-            q->steps_done += 1;
-            s->updates += q->r.n;
-            if (!ok || q->steps_done >= q->r.steps) finish(s, q, ok ? AUTOMAT_OK : AUTOMAT_EHIP);
-        }
+        if (!inflight.empty() && ((int)inflight.size() >= kInFlight || !launched))
+            retire_round(s, inflight);
     }
 }
 
@@ -633,7 +715,10 @@ extern "C" int32_t automat_server_create(size_t hbm_budget_bytes, int64_t max_ba
     int32_t rc = AUTOMAT_OK;
     if (hipGetDevice(&s->device) != hipSuccess || device_cus(&cus) != AUTOMAT_OK ||
         hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&s->up, hipStreamNonBlocking) != hipSuccess)
+        hipStreamCreateWithFlags(&s->up, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&s->down, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreate(&s->ev_start[0]) != hipSuccess || hipEventCreate(&s->ev_start[1]) != hipSuccess ||
+        hipEventCreate(&s->ev_end[0]) != hipSuccess || hipEventCreate(&s->ev_end[1]) != hipSuccess)
         rc = AUTOMAT_EHIP;
     else if (hipMalloc(&s->arena_base, s->budget) != hipSuccess)
         rc = AUTOMAT_ENOMEM;
@@ -641,6 +726,11 @@ extern "C" int32_t automat_server_create(size_t hbm_budget_bytes, int64_t max_ba
         (void)hipGetLastError();
         if (s->stream) (void)hipStreamDestroy(s->stream);
         if (s->up) (void)hipStreamDestroy(s->up);
+        if (s->down) (void)hipStreamDestroy(s->down);
+        for (int k = 0; k < 2; ++k) {
+            if (s->ev_start[k]) (void)hipEventDestroy(s->ev_start[k]);
+            if (s->ev_end[k]) (void)hipEventDestroy(s->ev_end[k]);
+        }
         delete s;
         return rc;
     }
@@ -725,15 +815,21 @@ extern "C" int32_t automat_server_destroy(automat_server *s) {
     if (s->worker.joinable()) s->worker.join();
     (void)hipStreamSynchronize(s->up);
     (void)hipStreamSynchronize(s->stream);
+    (void)hipStreamSynchronize(s->down);
     for (Req *q : s->active) {
         if (q->ready) (void)hipEventDestroy(q->ready);
         delete q;
     }
-    if (s->d_segs) (void)hipFree(s->d_segs);
-    if (s->h_segs) (void)hipHostFree(s->h_segs);
+    for (int k = 0; k < 2; ++k) {
+        if (s->d_segs[k]) (void)hipFree(s->d_segs[k]);
+        if (s->h_segs[k]) (void)hipHostFree(s->h_segs[k]);
+        if (s->ev_start[k]) (void)hipEventDestroy(s->ev_start[k]);
+        if (s->ev_end[k]) (void)hipEventDestroy(s->ev_end[k]);
+    }
     if (s->arena_base) (void)hipFree(s->arena_base);
     if (s->stream) (void)hipStreamDestroy(s->stream);
     if (s->up) (void)hipStreamDestroy(s->up);
+    if (s->down) (void)hipStreamDestroy(s->down);
     delete s;
     return AUTOMAT_OK;
 }
