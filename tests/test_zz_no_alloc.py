@@ -1,8 +1,8 @@
 """The basic-scheme load step without allocation (automat_ms_step_noalloc)
 against the step with the handle's own work space (automat_ms_step),
 through the C ABI: the same kernels run on the same inputs, so the fields,
-mean stresses, iteration counts and residuals agree exactly. Two calls in a
-row, the second on a smaller grid, and the rejections."""
+mean stresses, iteration counts and residuals agree exactly. Calls in a
+row, each on a smaller grid than the one before, and the rejections."""
 import numpy as np
 import pytest
 
@@ -43,8 +43,10 @@ def test_noalloc_step_equals_the_handle_step(warm):
     ph = inputs.paper_phases()
     h = 1.0
     loads = [[2e-3 * k, -5e-4 * k, 0, 0, 3e-4 * k, 0] for k in (1, 2)]
-    # first a 24 x 20 x 28 grid, then a smaller 12 x 10 x 16 one
-    for shape, seed in (((24, 20, 28), 3), ((12, 10, 16), 4)):
+    # a 4 x 128 x 128 grid (the plane transform kernels, z by hipFFT), then
+    # a smaller 24 x 20 x 28 one and a still smaller 12 x 10 x 16 one (3-D
+    # hipFFT plans)
+    for shape, seed in (((4, 128, 128), 2), ((24, 20, 28), 3), ((12, 10, 16), 4)):
         rng = np.random.default_rng(seed)
         phase = (rng.random(shape[0] * shape[1] * shape[2]) < 0.2).astype(np.uint8)
         opts = dict(tol=1e-8, max_iter=2000, warm_start=warm)
