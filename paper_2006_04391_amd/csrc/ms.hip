@@ -384,8 +384,15 @@ __global__ __launch_bounds__(kRedBlock) void mean6_kernel(const double *x, int64
 // sum of m partials per row (rows = gridDim.x, 256 threads per row) in a
 // fixed order: strided per-thread sums, then a tree over the threads, so the
 // result does not depend on timing
+// fold (optional, the step's failure counters): fold[0] += fold[1],
+// fold[1] = 0, by one thread (stream order makes it safe).
 __global__ __launch_bounds__(kRedBlock) void finish_kernel(const double *partial, int m,
-                                                           double *out) {
+                                                           double *out,
+                                                           uint64_t *fold = nullptr) {
+    if (fold && blockIdx.x == 0 && threadIdx.x == 0) {
+        fold[0] += fold[1];
+        fold[1] = 0;
+    }
     __shared__ double red[kRedBlock];
     double s = 0.0;
     for (int b = threadIdx.x; b < m; b += kRedBlock) s += partial[blockIdx.x * m + b];
@@ -558,7 +565,9 @@ struct automat_ms {
     hipfftDoubleComplex *spec;  // [6][nh]
     double *partial;            // [6 * kRedBlocks]
     double *scal;               // [16] reduced scalars; [8..13] the macro strain
-    uint64_t *fails;            // device: point solves of the current step that failed
+    uint64_t *fails;            // device [2]: point solves of the current step that failed,
+                                // and those of a sweep started ahead of a convergence test
+    hipEvent_t ev_scal;         // the reduced scalars have reached the host
     uint64_t *host_fails;       // pinned
     uint64_t last_fails;        // of the last completed step
     double *host_scal;          // pinned [16]
@@ -628,7 +637,8 @@ extern "C" int32_t automat_ms_create(int32_t nx, int32_t ny, int32_t nz,
               hipMalloc(&m->partial, 6 * kRedBlocks * sizeof(double)) == hipSuccess &&
               hipMalloc(&m->scal, 16 * sizeof(double)) == hipSuccess &&
               hipHostMalloc(&m->host_scal, 16 * sizeof(double), hipHostMallocDefault) == hipSuccess &&
-              hipMalloc(&m->fails, sizeof(uint64_t)) == hipSuccess &&
+              hipMalloc(&m->fails, 2 * sizeof(uint64_t)) == hipSuccess &&
+              hipEventCreateWithFlags(&m->ev_scal, hipEventDisableTiming) == hipSuccess &&
               hipHostMalloc(&m->host_fails, sizeof(uint64_t), hipHostMallocDefault) == hipSuccess;
     ok = ok && hipfftPlanMany(&m->fwd, 3, dims, dims, 1, (int)m->f.n, dims_c, 1, (int)m->f.nh,
                               HIPFFT_D2Z, 6) == HIPFFT_SUCCESS;
@@ -669,6 +679,7 @@ extern "C" int32_t automat_ms_destroy(automat_ms *m) {
     if (m->scal) (void)hipFree(m->scal);
     if (m->host_scal) (void)hipHostFree(m->host_scal);
     if (m->fails) (void)hipFree(m->fails);
+    if (m->ev_scal) (void)hipEventDestroy(m->ev_scal);
     if (m->host_fails) (void)hipHostFree(m->host_fails);
     if (m->tan) (void)hipFree(m->tan);
     if (m->lam) (void)hipFree(m->lam);
@@ -744,10 +755,10 @@ struct MsWork {
     hipfftDoubleComplex *spec;  // [6][nh]
     double *partial;            // [6 * kRedBlocks]
     double *scal;               // [16]
-    uint64_t *fails;            // [1]
+    uint64_t *fails;            // [2]
 };
 
-__global__ void zero_u64_kernel(uint64_t *p) { *p = 0; }
+__global__ void zero_u64_kernel(uint64_t *p) { p[0] = p[1] = 0; }
 
 static int32_t ms_step_impl(automat_ms *m, const MsWork &w, const uint8_t *phase,
                             const double *E_macro, const double *S_macro, uint32_t stress_mask,
@@ -795,12 +806,22 @@ static int32_t ms_step_impl(automat_ms *m, const MsWork &w, const uint8_t *phase
     }
     int it = 0;
     double err = 0.0;
+    // While the host waits for an iteration's convergence test, the next
+    // iteration's sweep (which reads only the updated strain) already runs;
+    // its failures go to the second counter and are folded in when it is
+    // used, and a converged step discards it.
+    bool ahead = false;
     for (it = 1; it <= m->opts.max_iter; ++it) {
+        const bool swept = ahead;
+        ahead = false;
         // material sweep writing the polarization tau = sigma - C0 eps
-        rc = evaluate_polarized(n, eps, a, phase, &m->params, h, m->opts.newton_tol,
-                                m->opts.newton_max_iter, m->lam0, m->mu0, w.sig, warm(m),
-                                w.fails, stream);
-        if (rc) return rc;
+        if (!swept) {
+            rc = evaluate_polarized(n, eps, a, phase, &m->params, h, m->opts.newton_tol,
+                                    m->opts.newton_max_iter, m->lam0, m->mu0, w.sig, warm(m),
+                                    w.fails, stream);
+            if (rc) return rc;
+        }
+        uint64_t *fold = swept ? w.fails : nullptr;
         if (m->slab) {
             const int64_t P = (int64_t)m->f.ny * (m->f.nx / 2 + 1);
             slab::cd *sp = reinterpret_cast<slab::cd *>(w.spec);
@@ -820,7 +841,7 @@ static int32_t ms_step_impl(automat_ms *m, const MsWork &w, const uint8_t *phase
             hipLaunchKernelGGL(xy_inverse_update_kernel, dim3(m->slab_grid), dim3(slab::kThreads),
                                0, s, sp, eps, m->f.nz, 1.0 / (double)n, w.partial);
             hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedBlock), 0, s, w.partial,
-                               m->slab_grid, w.scal);
+                               m->slab_grid, w.scal, fold);
         } else {
             if (hipfftExecD2Z(m->fwd, w.sig, w.spec) != HIPFFT_SUCCESS) return AUTOMAT_EHIP;
             hipLaunchKernelGGL(gamma_kernel, dim3(nhb), dim3(tb), 0, s, w.spec, m->f, m->lam0,
@@ -829,11 +850,21 @@ static int32_t ms_step_impl(automat_ms *m, const MsWork &w, const uint8_t *phase
             hipLaunchKernelGGL(update_kernel, dim3(rb), dim3(kRedBlock), 0, s, eps, w.sig, n,
                                w.partial);
             hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedBlock), 0, s, w.partial, rb,
-                               w.scal);
+                               w.scal, fold);
         }
         if (!m->opts.fixed_iter || it == m->opts.max_iter) {
-            rc = read_scalars(m, w.scal, 14, s);
-            if (rc) return rc;
+            if (hipMemcpyAsync(m->host_scal, w.scal, 14 * sizeof(double), hipMemcpyDeviceToHost,
+                               s) != hipSuccess ||
+                hipEventRecord(m->ev_scal, s) != hipSuccess)
+                return AUTOMAT_EHIP;
+            if (!m->opts.fixed_iter && it < m->opts.max_iter) {
+                rc = evaluate_polarized(n, eps, a, phase, &m->params, h, m->opts.newton_tol,
+                                        m->opts.newton_max_iter, m->lam0, m->mu0, w.sig, warm(m),
+                                        w.fails + 1, stream);
+                if (rc) return rc;
+                ahead = true;
+            }
+            if (hipEventSynchronize(m->ev_scal) != hipSuccess) return AUTOMAT_EHIP;
             for (int c = 0; c < 6; ++c) Ecur[c] = m->host_scal[8 + c];
             err = sqrt(m->host_scal[0] / (double)n) / fmax(tensor_norm(Ecur), 1e-300);
             if (!m->opts.fixed_iter && err <= m->opts.tol) break;
