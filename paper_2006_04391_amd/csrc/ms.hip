@@ -304,9 +304,14 @@ __global__ __launch_bounds__(slab::kThreads) void xy_forward_kernel(const double
     slab::init_twiddles(tw);
     __syncthreads();
     const int64_t plane = (int64_t)slab::N * slab::N, P = (int64_t)slab::N * slab::NH;
+    // each plane's rows are loaded while the previous plane is transformed
+    slab::cd v[16];
+    if ((int)blockIdx.x < 6 * nz) slab::load_rows(tau + (int64_t)blockIdx.x * plane, v);
     for (int p = blockIdx.x; p < 6 * nz; p += gridDim.x) {
         const int c = p / nz, z = p - c * nz;
-        slab::forward_plane(tau + p * plane, spec + ((int64_t)z * 6 + c) * P, L, tw);
+        const int pn = p + (int)gridDim.x;
+        slab::forward_plane(v, pn < 6 * nz ? tau + pn * plane : nullptr,
+                            spec + ((int64_t)z * 6 + c) * P, L, tw);
     }
 }
 

@@ -147,22 +147,30 @@ __device__ __forceinline__ void init_twiddles(cd *tw) {
     }
 }
 
-// One forward plane: src real [128][128] (x fastest), dst half spectrum
-// [128][65]. L: LDS plane, tw: twiddles. Ends with the plane written.
-__device__ __forceinline__ void forward_plane(const double *__restrict__ src, cd *__restrict__ dst,
-                                              cd *L, const cd *tw) {
+// One forward plane: v holds its rows (load_rows), dst receives the half
+// spectrum [128][65]; next (or null): the next plane, whose rows are loaded
+// into v once this plane's rows are in LDS. L: LDS plane, tw: twiddles.
+// The rows of a real plane as the radix-16 pass takes them: lane l of packed
+// row g gets x = 8 n1 + l of rows 2g (real part) and 2g + 1 (imaginary part).
+__device__ __forceinline__ void load_rows(const double *__restrict__ src, cd *v) {
+    const int t = threadIdx.x;
+    const int g = t >> 3, l = t & 7;
+    const double *r0 = src + (2 * g) * N, *r1 = r0 + N;
+#pragma unroll
+    for (int n1 = 0; n1 < 16; ++n1) v[n1] = {r0[8 * n1 + l], r1[8 * n1 + l]};
+}
+
+__device__ __forceinline__ void forward_plane(cd *v, const double *__restrict__ next,
+                                              cd *__restrict__ dst, cd *L, const cd *tw) {
     const int t = threadIdx.x;
     const int g = t >> 3, l = t & 7;  // packed row or column g, lane l of its 8
     {
-        // rows: radix-16 pass straight from memory
-        cd v[16];
-        const double *r0 = src + (2 * g) * N, *r1 = r0 + N;
-#pragma unroll
-        for (int n1 = 0; n1 < 16; ++n1) v[n1] = {r0[8 * n1 + l], r1[8 * n1 + l]};
+        // rows: radix-16 pass
         pass16<false>(v, l, tw);
         __syncthreads();  // the previous plane's last reads of L are done
 #pragma unroll
         for (int k1 = 0; k1 < 16; ++k1) L[g * LD + 8 * k1 + l] = v[k1];
+        if (next) load_rows(next, v);
     }
     __syncthreads();
     {
@@ -186,7 +194,8 @@ __device__ __forceinline__ void forward_plane(const double *__restrict__ src, cd
     {
         // columns: separate the two real rows of each packed row while
         // loading, radix-16 pass
-        cd v[16];
+        cd w[16];
+        cd *v = w;
         const bool odd = l & 1;  // y = 8 n1 + l has the parity of l
 #pragma unroll
         for (int n1 = 0; n1 < 16; ++n1) {
