@@ -48,6 +48,7 @@
 #include "automat.h"
 #include "host_common.hpp"
 #include "slab_fft.hpp"
+#include "zfft150.hpp"
 
 namespace automat {
 namespace {
@@ -202,9 +203,15 @@ __global__ void gamma_kernel(hipfftDoubleComplex *spec, MsField f, double lam0, 
 // radix-8 passes of slab_fft.hpp), keeps them in LDS between the forward
 // transform, the Green operator (the six components of one frequency
 // together) and the inverse transform, and writes them back in place.
-// Neighbouring work-groups share 128-byte lines; blocks are dispatched to
-// the eight XCDs in turn, so block b takes group (b % 8) G / 8 + b / 8 and
-// each XCD walks a contiguous range of groups.
+// Neighbouring work-groups share 128-byte lines, so each XCD walks a
+// contiguous range of groups (xcd_group).
+// Group of block b when blocks go to the eight XCDs in turn: XCD b mod 8
+// walks a contiguous range of the G groups (a bijection for any G).
+__device__ __forceinline__ int xcd_group(int b, int G) {
+    const int q = G / 8, rem = G % 8, x = b % 8;
+    return x * q + (x < rem ? x : rem) + b / 8;
+}
+
 constexpr int kZR = 4;
 constexpr int kZThreads = 6 * kZR * 8;
 constexpr int kZLD = slab::N + 1;
@@ -214,9 +221,7 @@ __global__ __launch_bounds__(kZThreads) void z_gamma_kernel(slab::cd *spec, MsFi
     __shared__ cd X[6 * kZR * kZLD];
     __shared__ cd tw[slab::N];
     slab::init_twiddles(tw);
-    const int G = (int)gridDim.x;
-    const int b = (int)blockIdx.x;
-    const int grp = G % 8 == 0 ? (b % 8) * (G / 8) + b / 8 : b;
+    const int grp = xcd_group((int)blockIdx.x, (int)gridDim.x);
     const int64_t P = (int64_t)slab::N * slab::NH;
     const int r0 = grp * kZR;
     const int t = threadIdx.x;
@@ -290,6 +295,98 @@ __global__ __launch_bounds__(kZThreads) void z_gamma_kernel(slab::cd *spec, MsFi
         for (int k2 = 0; k2 < 8; ++k2) {
             base[(int64_t)(l + 16 * k2) * 6 * P] = a[k2];
             base[(int64_t)(l + 8 + 16 * k2) * 6 * P] = bb[k2];
+        }
+    }
+}
+
+// The same for grids with nz = 150 (zfft150.hpp) on component-major spectra
+// (value c of frequency (kx, ky, kz) at c cs + kz zs + r, r = ky nxh + kx)
+// between 2-D in-plane hipFFT transforms: kZR frequencies r per
+// work-group, 16 lanes per column (ten of them in the radix-15 pass,
+// fifteen in the radix-10 pass).
+constexpr int kZ150Threads = 6 * kZR * 16;
+constexpr int kZ150LD = z150::N + 1;
+__global__ __launch_bounds__(kZ150Threads) void z150_gamma_kernel(hipfftDoubleComplex *spec,
+                                                                  MsField f, double lam0,
+                                                                  double mu0, MacroBC bc,
+                                                                  int64_t cs, int64_t zs) {
+    using slab::cd;
+    __shared__ cd X[6 * kZR * kZ150LD];
+    __shared__ cd tw[z150::N];
+    z150::init_twiddles(tw);
+    const int grp = xcd_group((int)blockIdx.x, (int)gridDim.x);
+    const int nxh = f.nx / 2 + 1;
+    const int r0 = grp * kZR;
+    const int t = threadIdx.x;
+    const int rr = t & (kZR - 1), l = (t / kZR) & 15, c = t / (kZR * 16);
+    const int col = c * kZR + rr;
+    cd *base = reinterpret_cast<cd *>(spec) + (int64_t)c * cs + r0 + rr;  // + z zs
+    cd *Xc = X + col * kZ150LD;
+    __syncthreads();
+    {
+        cd v[15];
+        if (l < 10) {
+#pragma unroll
+            for (int n1 = 0; n1 < 15; ++n1) v[n1] = base[(int64_t)(10 * n1 + l) * zs];
+            z150::pass15<false>(v, l, tw);
+#pragma unroll
+            for (int k1 = 0; k1 < 15; ++k1) Xc[10 * k1 + l] = v[k1];
+        }
+    }
+    __syncthreads();
+    {
+        cd v[10];
+        if (l < 15) {
+#pragma unroll
+            for (int n2 = 0; n2 < 10; ++n2) v[n2] = Xc[10 * l + n2];
+            z150::dft10<false>(v, tw);
+        }
+        __syncthreads();
+        if (l < 15) {
+#pragma unroll
+            for (int k2 = 0; k2 < 10; ++k2) Xc[l + 15 * k2] = v[k2];
+        }
+    }
+    __syncthreads();
+    for (int q = t; q < z150::N * kZR; q += kZ150Threads) {
+        const int kz = q / kZR, qr = q - kz * kZR;
+        const int r = r0 + qr;
+        const int ky = r / nxh, kx = r - ky * nxh;
+        hipfftDoubleComplex v6[6];
+        for (int cc = 0; cc < 6; ++cc) {
+            const cd x = X[(cc * kZR + qr) * kZ150LD + kz];
+            v6[cc].x = x.re;
+            v6[cc].y = x.im;
+        }
+        if (r == 0 && kz == 0)
+            gamma_zero(v6, f, lam0, mu0, bc);
+        else
+            gamma_point(v6, f, kx, ky, kz, lam0, mu0);
+        for (int cc = 0; cc < 6; ++cc) X[(cc * kZR + qr) * kZ150LD + kz] = {v6[cc].x, v6[cc].y};
+    }
+    __syncthreads();
+    {
+        cd v[15];
+        if (l < 10) {
+#pragma unroll
+            for (int n1 = 0; n1 < 15; ++n1) v[n1] = Xc[10 * n1 + l];
+            z150::pass15<true>(v, l, tw);
+        }
+        __syncthreads();
+        if (l < 10) {
+#pragma unroll
+            for (int k1 = 0; k1 < 15; ++k1) Xc[10 * k1 + l] = v[k1];
+        }
+    }
+    __syncthreads();
+    {
+        cd v[10];
+        if (l < 15) {
+#pragma unroll
+            for (int n2 = 0; n2 < 10; ++n2) v[n2] = Xc[10 * l + n2];
+            z150::dft10<true>(v, tw);
+#pragma unroll
+            for (int k2 = 0; k2 < 10; ++k2) base[(int64_t)(l + 15 * k2) * zs] = v[k2];
         }
     }
 }
@@ -564,6 +661,10 @@ struct automat_ms {
     bool slab, zfused;
     int slab_grid;
     hipfftHandle zfft;
+    // grids with nz = 150 (other in-plane sizes): 2-D hipFFT transforms over
+    // (y, x) and z150_gamma_kernel along z
+    bool z150;
+    hipfftHandle fwd2, inv2;
     double *sig;   // [6][n] stress / polarization / raw inverse FFT output
     double *dlt;   // [6][n] increments a_{n+1} - a_n of the last sweep: the next
                    // sweep's Newton solves start there (warm start)
@@ -664,6 +765,15 @@ extern "C" int32_t automat_ms_create(int32_t nx, int32_t ny, int32_t nz,
         ok = ok && (m->zfused || hipfftPlanMany(&m->zfft, 1, len, len, planes, 1, len, planes, 1,
                                                 HIPFFT_Z2Z, planes) == HIPFFT_SUCCESS);
     }
+    m->z150 = !m->slab && nz == z150::N && (int64_t)ny * (nx / 2 + 1) % kZR == 0;
+    if (ok && m->z150) {
+        int d2[2] = {ny, nx}, d2c[2] = {ny, nx / 2 + 1};
+        const int pr = ny * nx, pc = ny * (nx / 2 + 1);
+        ok = hipfftPlanMany(&m->fwd2, 2, d2, d2, 1, pr, d2c, 1, pc, HIPFFT_D2Z, 6 * nz) ==
+                 HIPFFT_SUCCESS &&
+             hipfftPlanMany(&m->inv2, 2, d2, d2c, 1, pc, d2, 1, pr, HIPFFT_Z2D, 6 * nz) ==
+                 HIPFFT_SUCCESS;
+    }
     if (!ok) {
         automat_ms_destroy(m);
         return AUTOMAT_ENOMEM;
@@ -677,6 +787,8 @@ extern "C" int32_t automat_ms_destroy(automat_ms *m) {
     if (m->fwd) (void)hipfftDestroy(m->fwd);
     if (m->inv) (void)hipfftDestroy(m->inv);
     if (m->zfft) (void)hipfftDestroy(m->zfft);
+    if (m->fwd2) (void)hipfftDestroy(m->fwd2);
+    if (m->inv2) (void)hipfftDestroy(m->inv2);
     if (m->sig) (void)hipFree(m->sig);
     if (m->dlt) (void)hipFree(m->dlt);
     if (m->spec) (void)hipFree(m->spec);
@@ -775,7 +887,9 @@ static int32_t ms_step_impl(automat_ms *m, const MsWork &w, const uint8_t *phase
     const int tb = 256;
     const int gb = (int)((n + tb - 1) / tb);
     if (hipfftSetStream(m->fwd, s) != HIPFFT_SUCCESS || hipfftSetStream(m->inv, s) != HIPFFT_SUCCESS ||
-        (m->zfft && hipfftSetStream(m->zfft, s) != HIPFFT_SUCCESS))
+        (m->zfft && hipfftSetStream(m->zfft, s) != HIPFFT_SUCCESS) ||
+        (m->fwd2 && (hipfftSetStream(m->fwd2, s) != HIPFFT_SUCCESS ||
+                     hipfftSetStream(m->inv2, s) != HIPFFT_SUCCESS)))
         return AUTOMAT_EHIP;
     hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, s, w.fails);
     MacroBC bc;
@@ -848,10 +962,18 @@ static int32_t ms_step_impl(automat_ms *m, const MsWork &w, const uint8_t *phase
             hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedBlock), 0, s, w.partial,
                                m->slab_grid, w.scal, fold);
         } else {
-            if (hipfftExecD2Z(m->fwd, w.sig, w.spec) != HIPFFT_SUCCESS) return AUTOMAT_EHIP;
-            hipLaunchKernelGGL(gamma_kernel, dim3(nhb), dim3(tb), 0, s, w.spec, m->f, m->lam0,
-                               m->mu0, bc, m->f.nh, (int64_t)m->f.ny * (m->f.nx / 2 + 1));
-            if (hipfftExecZ2D(m->inv, w.spec, w.sig) != HIPFFT_SUCCESS) return AUTOMAT_EHIP;
+            const int64_t P = (int64_t)m->f.ny * (m->f.nx / 2 + 1);
+            if (m->z150) {
+                if (hipfftExecD2Z(m->fwd2, w.sig, w.spec) != HIPFFT_SUCCESS) return AUTOMAT_EHIP;
+                hipLaunchKernelGGL(z150_gamma_kernel, dim3((int)(P / kZR)), dim3(kZ150Threads), 0,
+                                   s, w.spec, m->f, m->lam0, m->mu0, bc, m->f.nh, P);
+                if (hipfftExecZ2D(m->inv2, w.spec, w.sig) != HIPFFT_SUCCESS) return AUTOMAT_EHIP;
+            } else {
+                if (hipfftExecD2Z(m->fwd, w.sig, w.spec) != HIPFFT_SUCCESS) return AUTOMAT_EHIP;
+                hipLaunchKernelGGL(gamma_kernel, dim3(nhb), dim3(tb), 0, s, w.spec, m->f, m->lam0,
+                                   m->mu0, bc, m->f.nh, P);
+                if (hipfftExecZ2D(m->inv, w.spec, w.sig) != HIPFFT_SUCCESS) return AUTOMAT_EHIP;
+            }
             hipLaunchKernelGGL(update_kernel, dim3(rb), dim3(kRedBlock), 0, s, eps, w.sig, n,
                                w.partial);
             hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedBlock), 0, s, w.partial, rb,

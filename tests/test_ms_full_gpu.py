@@ -7,8 +7,9 @@ agree to rounding.
   iterations, cold Newton starts as in the benchmark;
 * 150^3 synthetic metal-matrix composite, the paper's phases, two steps of
   the tension-compression cycle under uniaxial mixed conditions with the
-  reference stiffness adjusted from the tangent field every step (hipFFT
-  plans of length 150 = 2 3 5^2), 10 iterations each;
+  reference stiffness adjusted from the tangent field every step (2-D
+  hipFFT plans in-plane, the length-150 z transforms with the Green
+  operator in one kernel), 10 iterations each;
 * the same on a 128^3 composite, 8 iterations each (the in-plane slab
   transforms and the fused z transform with the Green operator, whose
   zero frequency then carries the mixed conditions);

@@ -70,12 +70,13 @@ def test_laminate_exact():
 
 
 @pytest.mark.parametrize("shape", [(12, 12, 12), (6, 10, 12), (16, 12, 10), (32, 6, 9),
-                                   (8, 8, 8), (4, 128, 128), (3, 128, 128)])
+                                   (8, 8, 8), (4, 128, 128), (3, 128, 128), (150, 8, 6)])
 def test_lockstep_parity_viscoplastic(shape):
     """Fixed iteration counts on both sides: fields agree to rounding (odd
     and even extents, power-of-two and other lengths along every axis; the
     128 x 128 planes take the slab transforms, with z transforms of length 4
-    and 3)."""
+    and 3; nz = 150 takes the length-150 z transforms with the Green operator
+    between 2-D in-plane transforms)."""
     nz, ny, nx = shape
     rng = np.random.default_rng(7)
     phase = (rng.random(nz * ny * nx) < 0.2).astype(np.uint8)
@@ -189,7 +190,8 @@ def test_mixed_laminate_exact(mask):
 
 @pytest.mark.parametrize("shape,upd", [((12, 12, 12), True), ((6, 10, 12), True),
                                        ((7, 9, 10), False), ((16, 10, 12), True),
-                                       ((8, 7, 6), False), ((5, 128, 128), True)])
+                                       ((8, 7, 6), False), ((5, 128, 128), True),
+                                       ((150, 4, 10), True)])
 def test_lockstep_parity_mixed(shape, upd):
     """Uniaxial tension then compression under mixed conditions, the
     reference adjusted every step: fixed iteration counts on both sides,
