@@ -322,7 +322,17 @@ __device__ __forceinline__ void inverse_plane_update(const cd *__restrict__ src,
     }
     __syncthreads();
     {
-        // rows: radix-8 pass, then the update of rows 2g and 2g + 1
+        // rows: radix-8 pass, then the update of rows 2g and 2g + 1 (their
+        // old strain is loaded first, in flight during the pass)
+        double *e0 = eps + (2 * g) * N, *e1 = e0 + N;
+        double old0[16], old1[16];
+#pragma unroll
+        for (int k2 = 0; k2 < 8; ++k2)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                old0[2 * k2 + h] = e0[l + 8 * h + 16 * k2];
+                old1[2 * k2 + h] = e1[l + 8 * h + 16 * k2];
+            }
         cd a[8], b[8];
 #pragma unroll
         for (int n2 = 0; n2 < 8; ++n2) {
@@ -331,7 +341,6 @@ __device__ __forceinline__ void inverse_plane_update(const cd *__restrict__ src,
         }
         dft8<true>(a);
         dft8<true>(b);
-        double *e0 = eps + (2 * g) * N, *e1 = e0 + N;
 #pragma unroll
         for (int k2 = 0; k2 < 8; ++k2) {
 #pragma unroll
@@ -339,7 +348,7 @@ __device__ __forceinline__ void inverse_plane_update(const cd *__restrict__ src,
                 const cd z = h ? b[k2] : a[k2];
                 const int x = l + 8 * h + 16 * k2;
                 const double n0 = z.re * inv_n, n1v = z.im * inv_n;
-                const double d0 = n0 - e0[x], d1 = n1v - e1[x];
+                const double d0 = n0 - old0[2 * k2 + h], d1 = n1v - old1[2 * k2 + h];
                 acc += wgt * (d0 * d0 + d1 * d1);
                 e0[x] = n0;
                 e1[x] = n1v;
