@@ -12,8 +12,10 @@
 // request's next load step may follow its previous one, stream order keeps
 // them apart) before the scheduler waits for the older one, so the device
 // does not idle while the host retires a round and builds the next.
-// Requests that arrived meanwhile are admitted and their inputs uploaded on
-// a second stream (their first batch waits for an event); the results of
+// Requests that arrived meanwhile are admitted by a second host thread and
+// their inputs uploaded on a second stream (their first batch waits for an
+// event; a batch leaves out requests whose uploads are still running while
+// others are ready); the results of
 // finished requests are copied on a third stream once their last batch is
 // done, without waiting for the batch behind it. A
 // batch takes the requests with the least remaining work first (points
@@ -387,6 +389,9 @@ struct automat_server {
     std::vector<Req *> active;
     std::deque<automat_result> done;
     std::thread worker;
+    std::thread uploader;        // admissions: arena blocks and input uploads
+    int64_t uploading = 0;       // admitted requests whose uploads are being queued
+    uint64_t gen = 0;            // bumped by submissions and retirements
     bool stop = false;
     uint64_t next_id = 1;
     std::chrono::steady_clock::time_point t0;
@@ -405,17 +410,19 @@ struct automat_server {
     double busy_s = 0;
 };
 
-// Under s->mu: move requests from the head of the queue to the active set
-// while their blocks fit in the arena (arrival order, no overtaking).
+// Under s->mu: take requests from the head of the queue while their blocks
+// fit in the arena (arrival order, no overtaking); they join the active set
+// once their uploads are queued.
 static void take_admissible(automat_server *s, std::vector<Req *> &fresh) {
     const size_t max_active = s->sequential ? 1 : (size_t)1 << 20;
-    while (!s->stop && !s->pending.empty() && s->active.size() < max_active) {
+    while (!s->stop && !s->pending.empty() &&
+           s->active.size() + (size_t)s->uploading < max_active) {
         Req *q = s->pending.front();
         if (!s->arena.alloc(q->lay.total, &q->off)) break;
         s->pending.pop_front();
         q->last_round = s->round;
         s->used += q->lay.total;
-        s->active.push_back(q);
+        s->uploading += 1;
         fresh.push_back(q);
     }
 }
@@ -454,7 +461,9 @@ static void finish(automat_server *s, Req *q, int32_t status, hipEvent_t after =
     res.t_admit = q->t_admit;
     res.t_done = q->t_done;
     std::lock_guard<std::mutex> lock(s->mu);
-    s->active.erase(std::find(s->active.begin(), s->active.end(), q));
+    auto it = std::find(s->active.begin(), s->active.end(), q);
+    if (it != s->active.end()) s->active.erase(it);
+    s->gen += 1;
     s->arena.release(q->off, q->lay.total);
     s->used -= q->lay.total;
     s->done.push_back(res);
@@ -503,9 +512,34 @@ static void admit(automat_server *s, std::vector<Req *> &fresh) {
     });
     for (Req *q : fresh) {
         const int32_t rc = start_upload(s, q);
+        {
+            std::lock_guard<std::mutex> lock(s->mu);
+            s->uploading -= 1;
+            if (rc == AUTOMAT_OK) s->active.push_back(q);
+        }
         if (rc != AUTOMAT_OK) finish(s, q, rc);
+        s->cv.notify_all();
     }
     fresh.clear();
+}
+
+// The admission thread: takes the requests that fit and queues their
+// uploads (from pageable host memory these copies can block the calling
+// thread, so they stay off the batch scheduler's thread).
+static void uploader_loop(automat_server *s) {
+    (void)hipSetDevice(s->device);
+    std::vector<Req *> fresh;
+    uint64_t seen = ~(uint64_t)0;
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lock(s->mu);
+            s->cv.wait(lock, [&] { return s->stop || s->gen != seen; });
+            if (s->stop) return;
+            seen = s->gen;
+            take_admissible(s, fresh);
+        }
+        admit(s, fresh);
+    }
 }
 
 // batches a request may be left out of before it goes first
@@ -661,15 +695,16 @@ constexpr int kInFlight = 2;
 
 static void worker_loop(automat_server *s) {
     (void)hipSetDevice(s->device);
-    std::vector<Req *> fresh, order;
+    std::vector<Req *> order;
     std::deque<Round> inflight;
     for (;;) {
         {
             std::unique_lock<std::mutex> lock(s->mu);
             if (inflight.empty())
-                s->cv.wait(lock,
-                           [&] { return s->stop || !s->pending.empty() || !s->active.empty(); });
-            if (s->stop && s->active.empty() && inflight.empty()) {
+                s->cv.wait(lock, [&] {
+                    return !s->active.empty() || (s->stop && s->uploading == 0);
+                });
+            if (s->stop && s->active.empty() && s->uploading == 0 && inflight.empty()) {
                 for (Req *q : s->pending) {
                     automat_result res{};
                     res.id = q->id;
@@ -682,9 +717,7 @@ static void worker_loop(automat_server *s) {
                 s->pending.clear();
                 return;
             }
-            take_admissible(s, fresh);
         }
-        admit(s, fresh);
         bool launched = false;
         if ((int)inflight.size() < kInFlight) {
             Round r;
@@ -743,6 +776,7 @@ extern "C" int32_t automat_server_create(size_t hbm_budget_bytes, int64_t max_ba
         per_cu = 1;
     s->grid = cus * per_cu;
     s->worker = std::thread(worker_loop, s);
+    s->uploader = std::thread(uploader_loop, s);
     *out = s;
     return AUTOMAT_OK;
 }
@@ -774,6 +808,7 @@ extern "C" int32_t automat_server_submit(automat_server *s, const automat_reques
     q->id = s->next_id++;
     q->t_arrival = req->t_arrival >= 0.0 ? req->t_arrival : now_s(s->t0);
     s->pending.push_back(q);
+    s->gen += 1;
     *id = q->id;
     s->cv.notify_all();
     return AUTOMAT_OK;
@@ -812,6 +847,7 @@ extern "C" int32_t automat_server_destroy(automat_server *s) {
         s->stop = true;
         s->cv.notify_all();
     }
+    if (s->uploader.joinable()) s->uploader.join();
     if (s->worker.joinable()) s->worker.join();
     (void)hipStreamSynchronize(s->up);
     (void)hipStreamSynchronize(s->stream);
