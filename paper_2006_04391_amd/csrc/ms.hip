@@ -301,25 +301,26 @@ __global__ __launch_bounds__(kZThreads) void z_gamma_kernel(slab::cd *spec, MsFi
 
 // The same for grids with nz = 150 (zfft150.hpp) on component-major spectra
 // (value c of frequency (kx, ky, kz) at c cs + kz zs + r, r = ky nxh + kx)
-// between 2-D in-plane hipFFT transforms: kZR frequencies r per
+// between 2-D in-plane hipFFT transforms: kZ150R frequencies r per
 // work-group, 16 lanes per column (ten of them in the radix-15 pass,
 // fifteen in the radix-10 pass).
-constexpr int kZ150Threads = 6 * kZR * 16;
+constexpr int kZ150R = 8;  // eight frequencies: 128-byte segments per (z, c)
+constexpr int kZ150Threads = 6 * kZ150R * 16;
 constexpr int kZ150LD = z150::N + 1;
 __global__ __launch_bounds__(kZ150Threads) void z150_gamma_kernel(hipfftDoubleComplex *spec,
                                                                   MsField f, double lam0,
                                                                   double mu0, MacroBC bc,
                                                                   int64_t cs, int64_t zs) {
     using slab::cd;
-    __shared__ cd X[6 * kZR * kZ150LD];
+    __shared__ cd X[6 * kZ150R * kZ150LD];
     __shared__ cd tw[z150::N];
     z150::init_twiddles(tw);
     const int grp = xcd_group((int)blockIdx.x, (int)gridDim.x);
     const int nxh = f.nx / 2 + 1;
-    const int r0 = grp * kZR;
+    const int r0 = grp * kZ150R;
     const int t = threadIdx.x;
-    const int rr = t & (kZR - 1), l = (t / kZR) & 15, c = t / (kZR * 16);
-    const int col = c * kZR + rr;
+    const int rr = t & (kZ150R - 1), l = (t / kZ150R) & 15, c = t / (kZ150R * 16);
+    const int col = c * kZ150R + rr;
     cd *base = reinterpret_cast<cd *>(spec) + (int64_t)c * cs + r0 + rr;  // + z zs
     cd *Xc = X + col * kZ150LD;
     __syncthreads();
@@ -348,13 +349,13 @@ __global__ __launch_bounds__(kZ150Threads) void z150_gamma_kernel(hipfftDoubleCo
         }
     }
     __syncthreads();
-    for (int q = t; q < z150::N * kZR; q += kZ150Threads) {
-        const int kz = q / kZR, qr = q - kz * kZR;
+    for (int q = t; q < z150::N * kZ150R; q += kZ150Threads) {
+        const int kz = q / kZ150R, qr = q - kz * kZ150R;
         const int r = r0 + qr;
         const int ky = r / nxh, kx = r - ky * nxh;
         hipfftDoubleComplex v6[6];
         for (int cc = 0; cc < 6; ++cc) {
-            const cd x = X[(cc * kZR + qr) * kZ150LD + kz];
+            const cd x = X[(cc * kZ150R + qr) * kZ150LD + kz];
             v6[cc].x = x.re;
             v6[cc].y = x.im;
         }
@@ -362,7 +363,7 @@ __global__ __launch_bounds__(kZ150Threads) void z150_gamma_kernel(hipfftDoubleCo
             gamma_zero(v6, f, lam0, mu0, bc);
         else
             gamma_point(v6, f, kx, ky, kz, lam0, mu0);
-        for (int cc = 0; cc < 6; ++cc) X[(cc * kZR + qr) * kZ150LD + kz] = {v6[cc].x, v6[cc].y};
+        for (int cc = 0; cc < 6; ++cc) X[(cc * kZ150R + qr) * kZ150LD + kz] = {v6[cc].x, v6[cc].y};
     }
     __syncthreads();
     {
@@ -765,7 +766,7 @@ extern "C" int32_t automat_ms_create(int32_t nx, int32_t ny, int32_t nz,
         ok = ok && (m->zfused || hipfftPlanMany(&m->zfft, 1, len, len, planes, 1, len, planes, 1,
                                                 HIPFFT_Z2Z, planes) == HIPFFT_SUCCESS);
     }
-    m->z150 = !m->slab && nz == z150::N && (int64_t)ny * (nx / 2 + 1) % kZR == 0;
+    m->z150 = !m->slab && nz == z150::N && (int64_t)ny * (nx / 2 + 1) % kZ150R == 0;
     if (ok && m->z150) {
         int d2[2] = {ny, nx}, d2c[2] = {ny, nx / 2 + 1};
         const int pr = ny * nx, pc = ny * (nx / 2 + 1);
@@ -965,7 +966,7 @@ static int32_t ms_step_impl(automat_ms *m, const MsWork &w, const uint8_t *phase
             const int64_t P = (int64_t)m->f.ny * (m->f.nx / 2 + 1);
             if (m->z150) {
                 if (hipfftExecD2Z(m->fwd2, w.sig, w.spec) != HIPFFT_SUCCESS) return AUTOMAT_EHIP;
-                hipLaunchKernelGGL(z150_gamma_kernel, dim3((int)(P / kZR)), dim3(kZ150Threads), 0,
+                hipLaunchKernelGGL(z150_gamma_kernel, dim3((int)(P / kZ150R)), dim3(kZ150Threads), 0,
                                    s, w.spec, m->f, m->lam0, m->mu0, bc, m->f.nh, P);
                 if (hipfftExecZ2D(m->inv2, w.spec, w.sig) != HIPFFT_SUCCESS) return AUTOMAT_EHIP;
             } else {
