@@ -182,7 +182,7 @@ int32_t automat_evaluate_backward(int64_t n, const double *eps_new, const double
  * fixed or adjusted to the tangent field at the start of every load step
  * (paragraph "Material Law Evaluations").
  * ------------------------------------------------------------------------ */
-typedef struct automat_ms automat_ms; /* opaque; owns hipFFT plans and work buffers */
+typedef struct automat_ms automat_ms; /* opaque; owns its FFT plans and work buffers */
 
 typedef struct automat_ms_options {
     double tol;              /* stop when ||eps' - eps||_2 / ||E|| <= tol (tensor norms,
