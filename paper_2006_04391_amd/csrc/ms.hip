@@ -678,6 +678,9 @@ struct automat_ms {
     uint64_t *host_fails;       // pinned
     uint64_t last_fails;        // of the last completed step
     double *host_scal;          // pinned [16]
+    // the fixed-point iteration's scalars (norm at [0], macro strain at
+    // [8..13]), written by the kernels straight into pinned host memory
+    double *iter_host, *iter_dev;
     // reverse step work space, allocated on first use
     double *tan;                // [36][n] consistent tangent at the converged strain
     double *lam;                // [6][n] adjoint field
@@ -744,6 +747,10 @@ extern "C" int32_t automat_ms_create(int32_t nx, int32_t ny, int32_t nz,
               hipMalloc(&m->partial, 6 * kRedBlocks * sizeof(double)) == hipSuccess &&
               hipMalloc(&m->scal, 16 * sizeof(double)) == hipSuccess &&
               hipHostMalloc(&m->host_scal, 16 * sizeof(double), hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&m->iter_host, 16 * sizeof(double),
+                            hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
+              hipHostGetDevicePointer(reinterpret_cast<void **>(&m->iter_dev), m->iter_host, 0) ==
+                  hipSuccess &&
               hipMalloc(&m->fails, 2 * sizeof(uint64_t)) == hipSuccess &&
               hipEventCreateWithFlags(&m->ev_scal, hipEventDisableTiming) == hipSuccess &&
               hipHostMalloc(&m->host_fails, sizeof(uint64_t), hipHostMallocDefault) == hipSuccess;
@@ -796,6 +803,7 @@ extern "C" int32_t automat_ms_destroy(automat_ms *m) {
     if (m->partial) (void)hipFree(m->partial);
     if (m->scal) (void)hipFree(m->scal);
     if (m->host_scal) (void)hipHostFree(m->host_scal);
+    if (m->iter_host) (void)hipHostFree(m->iter_host);
     if (m->fails) (void)hipFree(m->fails);
     if (m->ev_scal) (void)hipEventDestroy(m->ev_scal);
     if (m->host_fails) (void)hipHostFree(m->host_fails);
@@ -899,7 +907,7 @@ static int32_t ms_step_impl(automat_ms *m, const MsWork &w, const uint8_t *phase
         bc.S[c] = S_macro ? S_macro[c] : 0.0;
     }
     bc.mask = stress_mask;
-    bc.Eout = w.scal + 8;
+    bc.Eout = m->iter_dev + 8;
     // initial guess: previous strain field shifted by the prescribed strain
     // increments and, on stress-controlled components, the increments that
     // keep the reference medium's stress there unchanged
@@ -961,7 +969,7 @@ static int32_t ms_step_impl(automat_ms *m, const MsWork &w, const uint8_t *phase
             hipLaunchKernelGGL(xy_inverse_update_kernel, dim3(m->slab_grid), dim3(slab::kThreads),
                                0, s, sp, eps, m->f.nz, 1.0 / (double)n, w.partial);
             hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedBlock), 0, s, w.partial,
-                               m->slab_grid, w.scal, fold);
+                               m->slab_grid, m->iter_dev, fold);
         } else {
             const int64_t P = (int64_t)m->f.ny * (m->f.nx / 2 + 1);
             if (m->z150) {
@@ -978,13 +986,11 @@ static int32_t ms_step_impl(automat_ms *m, const MsWork &w, const uint8_t *phase
             hipLaunchKernelGGL(update_kernel, dim3(rb), dim3(kRedBlock), 0, s, eps, w.sig, n,
                                w.partial);
             hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedBlock), 0, s, w.partial, rb,
-                               w.scal, fold);
+                               m->iter_dev, fold);
         }
         if (!m->opts.fixed_iter || it == m->opts.max_iter) {
-            if (hipMemcpyAsync(m->host_scal, w.scal, 14 * sizeof(double), hipMemcpyDeviceToHost,
-                               s) != hipSuccess ||
-                hipEventRecord(m->ev_scal, s) != hipSuccess)
-                return AUTOMAT_EHIP;
+            // the scalars are in host memory once this iteration's kernels are done
+            if (hipEventRecord(m->ev_scal, s) != hipSuccess) return AUTOMAT_EHIP;
             if (!m->opts.fixed_iter && it < m->opts.max_iter) {
                 rc = evaluate_polarized(n, eps, a, phase, &m->params, h, m->opts.newton_tol,
                                         m->opts.newton_max_iter, m->lam0, m->mu0, w.sig, warm(m),
@@ -993,8 +999,9 @@ static int32_t ms_step_impl(automat_ms *m, const MsWork &w, const uint8_t *phase
                 ahead = true;
             }
             if (hipEventSynchronize(m->ev_scal) != hipSuccess) return AUTOMAT_EHIP;
-            for (int c = 0; c < 6; ++c) Ecur[c] = m->host_scal[8 + c];
-            err = sqrt(m->host_scal[0] / (double)n) / fmax(tensor_norm(Ecur), 1e-300);
+            volatile const double *hs = m->iter_host;
+            for (int c = 0; c < 6; ++c) Ecur[c] = hs[8 + c];
+            err = sqrt(hs[0] / (double)n) / fmax(tensor_norm(Ecur), 1e-300);
             if (!m->opts.fixed_iter && err <= m->opts.tol) break;
         }
     }
