@@ -36,6 +36,7 @@ BYTES_PER_POINT_TANGENT = BYTES_PER_POINT + 36 * 8            # 481
 # FETCH_SIZE / WRITE_SIZE (scaled by a 1 GiB copy calibration), keyed by the
 # hash of the kernel sources they were taken on; a changed kernel reports
 # traffic null until it is measured again.
+MS_BYTES_PER_VOXEL = 581
 MEASURED_TRAFFIC = {"043ec1a872f2ddb2": 3.355e9}
 # Executed FP64 FLOP per point of the forward kernel on the 256^3 batch
 # (rocprofv3 SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes / points), same keying.
@@ -225,7 +226,15 @@ def ms_bench(steps, N=128, h=0.1, tol=1e-6):
                         f"uniaxial strain rate 1e-3/s, {steps} steps of h={h} s, tol {tol}, "
                         f"cold Newton starts",
             "wall_s": wall, "iterations": iters, "ms_per_iteration": wall / total * 1e3,
-            "sweep_updates_per_s": total * n / wall, "sigma_mean_last": mean}
+            "sweep_updates_per_s": total * n / wall, "sigma_mean_last": mean,
+            # algorithmic HBM bytes per voxel and iteration on grids with
+            # 128 x 128 planes: sweep 241, forward plane transforms 97, z
+            # transforms with the Green operator 98, inverse plane transforms
+            # with the strain update 145
+            "roofline": {"bound": "hbm", "bytes_per_voxel_iteration": MS_BYTES_PER_VOXEL,
+                         "achieved": MS_BYTES_PER_VOXEL * n * total / wall / 1e9,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": MS_BYTES_PER_VOXEL * n * total / wall / 1e9 / HBM_PEAK_GBS}}
 
 
 def ms_tc_bench(steps, N=150, tol=1e-6):
