@@ -17,7 +17,6 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libautomat.so")
 
 SOURCES = ["automat.hip", "backward.hip", "ms.hip", "server.hip", "rk23.hip", "conventional.hip", "f32.hip"]
-HEADERS = ["ad.hpp", "linalg6.hpp", "msgsm.hpp", "gsm_point.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
