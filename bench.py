@@ -46,15 +46,18 @@ KERNEL_SOURCES = ["automat.hip", "ad.hpp", "fastmath.hpp", "linalg6.hpp", "msgsm
 
 
 def kernel_source_hash():
-    """Hash of the forward kernel's sources and of the build script (its
-    compiler flags change the code too)."""
+    """Hash of the forward kernel's sources and of the compiler command line
+    they are built with (the flags change the code too)."""
     import hashlib
+    from paper_2006_04391_amd import build
     h = hashlib.sha256()
     for fn in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2006_04391_amd", "csrc", fn), "rb") as f:
             h.update(f.read())
-    with open(os.path.join(ROOT, "paper_2006_04391_amd", "build.py"), "rb") as f:
-        h.update(f.read())
+    flags = build._flags()
+    # include paths differ from one checkout to another; the rest is the code
+    kept = [f for k, f in enumerate(flags) if f != "-I" and (k == 0 or flags[k - 1] != "-I")]
+    h.update(" ".join(kept).encode())
     return h.hexdigest()[:16]
 
 
