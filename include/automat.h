@@ -381,7 +381,9 @@ typedef struct automat_server_stats_t {
  * max_batch_points (0 = unbounded) bounds the points of one launch (at least
  * one request is always taken; requests with the least remaining work, points
  * times load steps left, go first, and one left out of 16 consecutive
- * launches goes before all others); sequential != 0 admits one request at a
+ * launches goes before all others; while the next queued request waits for
+ * arena space a launch may take four times as many points, since the device
+ * is saturated then); sequential != 0 admits one request at a
  * time (the per-request baseline). Errors: AUTOMAT_EINVAL, AUTOMAT_ENOMEM
  * (the budget cannot be allocated), AUTOMAT_EHIP. */
 int32_t automat_server_create(size_t hbm_budget_bytes, int64_t max_batch_points,

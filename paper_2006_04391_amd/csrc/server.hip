@@ -391,6 +391,7 @@ struct automat_server {
     std::thread worker;
     std::thread uploader;        // admissions: arena blocks and input uploads
     int64_t uploading = 0;       // admitted requests whose uploads are being queued
+    bool blocked = false;        // the next request in line does not fit the arena
     uint64_t gen = 0;            // bumped by submissions and retirements
     bool stop = false;
     uint64_t next_id = 1;
@@ -415,10 +416,14 @@ struct automat_server {
 // once their uploads are queued.
 static void take_admissible(automat_server *s, std::vector<Req *> &fresh) {
     const size_t max_active = s->sequential ? 1 : (size_t)1 << 20;
+    s->blocked = false;
     while (!s->stop && !s->pending.empty() &&
            s->active.size() + (size_t)s->uploading < max_active) {
         Req *q = s->pending.front();
-        if (!s->arena.alloc(q->lay.total, &q->off)) break;
+        if (!s->arena.alloc(q->lay.total, &q->off)) {
+            s->blocked = true;
+            break;
+        }
         s->pending.pop_front();
         q->last_round = s->round;
         s->used += q->lay.total;
@@ -544,6 +549,8 @@ static void uploader_loop(automat_server *s) {
 
 // batches a request may be left out of before it goes first
 constexpr int64_t kAging = 16;
+// point cap multiplier while the next request waits for arena space
+constexpr int64_t kSaturatedCap = 4;
 
 // a launched batch that is not retired yet
 struct Round {
@@ -596,11 +603,16 @@ static void build_batch(automat_server *s, std::vector<Req *> &order, std::vecto
         if (starved(a) != starved(b)) return starved(a);
         return remaining(a) < remaining(b);
     });
+    // While requests wait in the queue (for arena space, or for the
+    // admission thread) the device is saturated and larger batches (fewer
+    // launches) pay; otherwise the cap keeps batches short, so that a
+    // request arriving meanwhile does not wait behind a long one.
+    const bool backlog = s->blocked || !s->pending.empty();
+    const int64_t cap = backlog ? kSaturatedCap * s->max_batch_points : s->max_batch_points;
     int64_t pts = 0;
     for (Req *q : order) {
         if (batch.size() >= (size_t)kMaxSegs) break;
-        if (!batch.empty() && s->max_batch_points > 0 && pts + q->r.n > s->max_batch_points)
-            continue;
+        if (!batch.empty() && cap > 0 && pts + q->r.n > cap) continue;
         batch.push_back(q);
         pts += q->r.n;
         q->last_round = rnd;
