@@ -573,8 +573,8 @@ def main():
         sv = {"workload": f"{len(serve_reqs)} requests, Poisson arrivals 200/s, cube side "
                           "log-uniform in [32, 256], fibre or sphere microstructure, phase "
                           "parameters jittered +-10 %, 1-10 load steps each, HBM budget 200 GB; "
-                          f"batched launches capped at {args.serve_cap} points, least remaining "
-                          "work first"}
+                          f"batched launches capped at {args.serve_cap} points (four times that "
+                          "while requests wait in the queue), least remaining work first"}
         for saturate in (False, True):
             for sequential in (False, True):
                 r = serve.replay(serve_reqs, serve_fields, sequential=sequential,
