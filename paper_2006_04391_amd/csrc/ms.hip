@@ -8,10 +8,19 @@
 //
 //   tau     = material(eps, a_n) - C0 eps              (one evaluation sweep
 //                                                       writing the polarization)
-//   tau^    = FFT(tau)                                 (6 batched D2Z)
+//   tau^    = FFT(tau)                                 (6 fields)
 //   eps^(xi)= -Gamma0(xi) : tau^(xi), xi != 0;  eps^(0) = E
-//   eps'    = IFFT(eps^) / N                           (6 batched Z2D)
+//   eps'    = IFFT(eps^) / N
 //   err     = ||eps' - eps||_2 / ||E||
+//
+// The transforms: on grids with 128 x 128 planes, plane transforms of our
+// own (slab_fft.hpp) with the strain update and its norm in the inverse
+// pass, and along z either one kernel with Gamma0 between the forward and
+// inverse transforms (nz = 128) or hipFFT with gamma_kernel between; on
+// grids with nz = 150, 2-D hipFFT transforms in-plane and one kernel along
+// z with Gamma0 (zfft150.hpp); otherwise 6-batch 3-D hipFFT plans with
+// gamma_kernel and update_kernel. While the host reads an iteration's norm
+// for the convergence test, the next iteration's sweep already runs.
 //
 // with Gamma0_khij = [d_ki q_h q_j + d_hi q_k q_j + d_kj q_h q_i +
 // d_hj q_k q_i] / (4 mu0) - (lambda0 + mu0) / (mu0 (lambda0 + 2 mu0))
