@@ -66,15 +66,24 @@ def log(*a):
 
 
 def time_calls(fn, steps, warmup, stream):
+    """Time `steps` calls back to back (events on the launch stream around the
+    whole loop: total_ms; host clock: wall), then the same number of calls
+    with events around each (each, per-launch durations)."""
     import torch
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
-    per = []
     t0 = time.perf_counter()
     start.record(stream)
+    for _ in range(steps):
+        fn()
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = start.elapsed_time(end)
+    per = []
     for _ in range(steps):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -82,10 +91,7 @@ def time_calls(fn, steps, warmup, stream):
         fn()
         e1.record(stream)
         per.append((e0, e1))
-    end.record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    total_ms = start.elapsed_time(end)
     each = [a.elapsed_time(b) for a, b in per]
     return total_ms, each, wall
 
@@ -292,7 +298,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--side", type=int, default=256, help="cube side (256 = the headline batch)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-tangent", action="store_true", help="skip the tangent variant")
