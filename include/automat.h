@@ -329,11 +329,12 @@ int32_t automat_ms_destroy(automat_ms *ms);
  * Requests of uneven sizes, each with several load steps and its own phase
  * table, are admitted in arrival order while their device block (97 bytes
  * per point plus the phase tables) fits in the server's arena, one device
- * allocation of the whole budget made at creation. Every round launches one
- * kernel over the next load step of every admitted request; requests that
- * arrive meanwhile are uploaded on a second stream while that kernel runs
- * and join the next round. Internal variables stay on the device between
- * steps. The strain of step j of K at point i is (j / K) E_final +
+ * allocation of the whole budget made at creation. Every batch is one
+ * kernel over the next load step of admitted requests (the least remaining
+ * work first, up to the point cap); the next batch is queued behind the
+ * running one; requests that arrive meanwhile are admitted by a second host
+ * thread, uploaded on a second stream while the kernels run, and join a
+ * later batch. Internal variables stay on the device between steps. The strain of step j of K at point i is (j / K) E_final +
  * noise_std z, z standard normal from Philox4x32-10 (Salmon et al. 2011)
  * keyed by seed with counter (i, j, w) and the Box-Muller transform.
  * Results do not depend on the rest of the batch beyond rounding (flowing
@@ -341,8 +342,9 @@ int32_t automat_ms_destroy(automat_ms *ms);
  * trial point is evaluated to first order; measured differences stay below
  * 1e-12 relative).
  * ------------------------------------------------------------------------ */
-typedef struct automat_server automat_server; /* opaque; owns a scheduler thread, two streams
-                                                 and the arena */
+typedef struct automat_server automat_server; /* opaque; owns a scheduler thread, an
+                                                 admission thread, three streams and
+                                                 the arena */
 
 typedef struct automat_request {
     int64_t n;             /* points, >= 1 */
