@@ -36,7 +36,15 @@ BYTES_PER_POINT_TANGENT = BYTES_PER_POINT + 36 * 8            # 481
 # FETCH_SIZE / WRITE_SIZE (scaled by a 1 GiB copy calibration), keyed by the
 # hash of the kernel sources they were taken on; a changed kernel reports
 # traffic null until it is measured again.
-MS_BYTES_PER_VOXEL = 581
+# Algorithmic HBM bytes per voxel and iteration of the basic scheme on grids
+# with 128 x 128 planes and cold Newton starts: the half spectrum of six
+# components is 6 x 65 x 16 B per 128 voxels (48.75 B); sweep 145 (reads eps,
+# a_n and the phase, writes tau), forward plane transforms 96.75 (tau in, half
+# spectrum out), z transforms with the Green operator 97.5, inverse plane
+# transforms with the strain update 144.75 (half spectrum and eps in, eps out).
+MS_HALF_SPECTRUM_BYTES = 6 * 65 * 16 / 128
+MS_BYTES_PER_VOXEL = ((48 + 48 + 1 + 48) + (48 + MS_HALF_SPECTRUM_BYTES)
+                      + 2 * MS_HALF_SPECTRUM_BYTES + (MS_HALF_SPECTRUM_BYTES + 48 + 48))   # 484
 MEASURED_TRAFFIC = {"6ef8e1e4fd952fd2": 3.352e9}
 # Executed FP64 FLOP per point of the forward kernel on the 256^3 batch
 # (rocprofv3 SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes / points), same keying.
@@ -236,10 +244,6 @@ def ms_bench(steps, N=128, h=0.1, tol=1e-6):
                         f"cold Newton starts",
             "wall_s": wall, "iterations": iters, "ms_per_iteration": wall / total * 1e3,
             "sweep_updates_per_s": total * n / wall, "sigma_mean_last": mean,
-            # algorithmic HBM bytes per voxel and iteration on grids with
-            # 128 x 128 planes: sweep 241, forward plane transforms 97, z
-            # transforms with the Green operator 98, inverse plane transforms
-            # with the strain update 145
             "roofline": {"bound": "hbm", "bytes_per_voxel_iteration": MS_BYTES_PER_VOXEL,
                          "achieved": MS_BYTES_PER_VOXEL * n * total / wall / 1e9,
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
