@@ -83,7 +83,8 @@ struct Segment {
     uint32_t step;
     int32_t max_iter;
     int32_t n_phases;
-    int32_t reserved;
+    int32_t a_zero;  // first load step of a request without an initial state:
+                     // a_n = 0 is not read, and points without flow write it
 };
 
 static_assert(sizeof(Segment) % sizeof(double) == 0, "Segment is copied as doubles");
@@ -118,9 +119,12 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double &z0, d
     z1 = r * s;
 }
 
-__global__ void build_tables_kernel(const Model::Phase *raw, int nph, PC *out) {
+// A request's phase tables at admission; also clears its failure counter.
+__global__ void build_tables_kernel(const Model::Phase *raw, int nph, PC *out,
+                                    unsigned long long *nonconv) {
     const int k = threadIdx.x;
     if (k < nph) build_phase_const<Model>(raw[k], out[k], false);
+    if (k == 0) *nonconv = 0ull;
 }
 
 // Segments per launch: their first-tile indices are staged in LDS.
@@ -235,7 +239,7 @@ void serve_batch_kernel(const Segment *segs, const int32_t *starts, int nseg, in
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
                 e[c] = sg.E[c] + sg.noise * z[c];
-                a[c] = sg.a[c * n + i];
+                a[c] = sg.a_zero ? 0.0 : sg.a[c * n + i];
                 finite_in = finite_in && isfinite(e[c]) && isfinite(a[c]);
             }
             pid = sg.phase[i];
@@ -247,6 +251,10 @@ void serve_batch_kernel(const Segment *segs, const int32_t *starts, int nseg, in
                 double sig[6];
                 if (valid) {
                     Model::stress(pc.prm, e, a, sig);
+                    if (sg.a_zero) {
+#pragma unroll
+                        for (int c = 0; c < 6; ++c) sg.a[c * n + i] = 0.0;
+                    }
                 } else {
 #pragma unroll
                     for (int c = 0; c < 6; ++c) {
@@ -367,6 +375,7 @@ struct Req {
     hipEvent_t ready = nullptr;  // uploads and table build done
     int32_t steps_done = 0;      // load steps of retired batches
     int32_t steps_launched = 0;  // load steps of launched batches
+    bool a_zero = false;         // no initial state: the first step takes a_n = 0
     int64_t last_round = 0;      // round of the last batch that took a step of it
     double t_arrival = 0, t_admit = 0, t_done = 0;
     int32_t status = 0;
@@ -493,17 +502,17 @@ static int32_t start_upload(automat_server *s, Req *q) {
         return AUTOMAT_EHIP;
     }
     const size_t abytes = (size_t)n * 6 * sizeof(double);
+    // without an initial state the first load step writes a_n = 0 itself
+    q->a_zero = q->r.a_init == nullptr;
     bool ok = hipMemcpyAsync(q->d_phase, q->r.phase, (size_t)n, hipMemcpyHostToDevice, s->up) ==
                   hipSuccess &&
-              (q->r.a_init ? hipMemcpyAsync(q->d_a, q->r.a_init, abytes, hipMemcpyHostToDevice,
-                                            s->up)
-                           : hipMemsetAsync(q->d_a, 0, abytes, s->up)) == hipSuccess &&
-              hipMemsetAsync(q->d_nonconv, 0, sizeof(unsigned long long), s->up) == hipSuccess &&
+              (!q->r.a_init || hipMemcpyAsync(q->d_a, q->r.a_init, abytes,
+                                              hipMemcpyHostToDevice, s->up) == hipSuccess) &&
               hipMemcpyAsync(q->d_raw, q->raw, (size_t)q->nph * sizeof(Model::Phase),
                              hipMemcpyHostToDevice, s->up) == hipSuccess;
     if (ok) {
         hipLaunchKernelGGL(build_tables_kernel, dim3(1), dim3(64), 0, s->up, q->d_raw, q->nph,
-                           q->d_tab);
+                           q->d_tab, q->d_nonconv);
         ok = hipGetLastError() == hipSuccess && hipEventRecord(q->ready, s->up) == hipSuccess;
     }
     return ok ? AUTOMAT_OK : AUTOMAT_EHIP;
@@ -649,7 +658,7 @@ static bool launch_round(automat_server *s, Round &r) {
         g.step = (uint32_t)step;
         g.max_iter = q->r.max_iter;
         g.n_phases = q->nph;
-        g.reserved = 0;
+        g.a_zero = q->a_zero && q->steps_launched == 0;
         tiles += (q->r.n + kBlock - 1) / kBlock;
     }
     const int nseg = (int)r.batch.size();

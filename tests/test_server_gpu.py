@@ -46,7 +46,7 @@ def _request(side, structure, seed, steps, phases=None, noise=2e-4, E=(5e-3, 0, 
 
 def _oracle_final(q, h=0.1, max_iter=50):
     n = q["phase"].size
-    a = np.zeros((6, n))
+    a = np.zeros((6, n)) if q.get("a_init") is None else np.array(q["a_init"], dtype=np.float64)
     fails = 0
     for j in range(1, q["steps"] + 1):
         eps = inputs.served_strain(n, j, q["steps"], q["E_final"], q["noise_std"], q["seed"])
@@ -134,6 +134,37 @@ def test_budget_admission_and_rejection():
         srv.submit(**big)
     assert e.value.code == _lib.EBUDGET
     srv.close()
+
+
+def test_first_step_state_in_a_reused_block():
+    """A request without an initial state starts from a_n = 0: its first load
+    step takes a_n = 0 without reading the field and writes the zeros of its
+    points without flow itself, so what an earlier request left in the same
+    arena block does not leak in (here the block of a request whose matrix
+    flowed, reused by one whose inclusions sit where that matrix was). A
+    request with an initial state starts from it."""
+    side = 16
+    n = side ** 3
+    first = _request(side, "sphere", 71, 3)
+    second = _request(side, "fibre", 72, 1)
+    a0 = inputs.deviatoric_draw(n, 1e-3, np.random.default_rng(73))
+    third = dict(_request(side, "sphere", 74, 2), a_init=a0)
+    srv = _server(budget=n * 97 + 8192)    # one request at a time, each in the block before
+    ids = [srv.submit(**q, want_fields=True) for q in (first, second, third)]
+    out = _drain(srv, ids)
+    srv.close()
+    finals = []
+    for q, r in zip((first, second, third), out):
+        assert r["status"] == 0
+        sig, a, fails = _oracle_final(q)
+        assert r["nonconverged"] == fails == 0
+        _check(r, sig, a)
+        finals.append(a)
+    kinds = np.array([p["kind"] for p in second["phases"]])
+    leftover = (np.abs(finals[0]).max(axis=0) > 0) & (kinds[second["phase"]] == 0)
+    assert leftover.sum() > 0
+    assert np.all(out[1]["a"][:, leftover] == 0.0)
+    assert not np.array_equal(finals[2], _oracle_final(dict(third, a_init=None))[1])
 
 
 def test_nonconverged_points_are_counted():
