@@ -45,10 +45,10 @@ BYTES_PER_POINT_TANGENT = BYTES_PER_POINT + 36 * 8            # 481
 MS_HALF_SPECTRUM_BYTES = 6 * 65 * 16 / 128
 MS_BYTES_PER_VOXEL = ((48 + 48 + 1 + 48) + (48 + MS_HALF_SPECTRUM_BYTES)
                       + 2 * MS_HALF_SPECTRUM_BYTES + (MS_HALF_SPECTRUM_BYTES + 48 + 48))   # 484
-MEASURED_TRAFFIC = {"6ef8e1e4fd952fd2": 3.352e9}
+MEASURED_TRAFFIC = {"f48d9ced49bd27d1": 3.351e9}
 # Executed FP64 FLOP per point of the forward kernel on the 256^3 batch
 # (rocprofv3 SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes / points), same keying.
-MEASURED_FP64_FLOP_PER_POINT = {"6ef8e1e4fd952fd2": 1119.0}
+MEASURED_FP64_FLOP_PER_POINT = {"f48d9ced49bd27d1": 1119.0}
 KERNEL_SOURCES = ["automat.hip", "ad.hpp", "fastmath.hpp", "linalg6.hpp", "msgsm.hpp",
                   "gsm_point.hpp", "gsm_kernel.hpp"]
 

@@ -464,7 +464,14 @@ static int32_t launch_evaluate(int64_t n, const double *eps_new, const double *a
     // Two (tangent: four) rounds of resident blocks: blocks that finish
     // early are replaced by the dispatcher, which evens out the end of the
     // launch (two waves share a SIMD and one of them gets issue priority).
-    const int64_t cap = (int64_t)dev.cus * (tangent_out ? 4 * dev.blocks_tan : 2 * dev.blocks_fwd);
+    // Below about 24 chunks per wave in one round (some 3 million points)
+    // each block's start (its phase tables) and each wave's partly filled
+    // last batch cost more than the uneven end: one round.
+    const int64_t chunks = (n + 63) / 64;
+    const int64_t one_round = (int64_t)dev.cus * dev.blocks_fwd;
+    const int rounds = chunks < 24 * one_round * kWaves ? 1 : 2;
+    const int64_t cap =
+        (int64_t)dev.cus * (tangent_out ? 4 * dev.blocks_tan : rounds * dev.blocks_fwd);
     const int grid = (int)(tiles < cap ? tiles : cap);
     const size_t smem = eval_smem_bytes(args.n_phases);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
