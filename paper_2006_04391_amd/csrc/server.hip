@@ -30,7 +30,10 @@
 // tiles of all segments. A tile belongs to one segment: the block finds it
 // from LDS-staged first-tile indices and keeps that request's descriptor and
 // phase table in LDS. Each lane generates the step's strain for its point
-// and loads a_n; points without flow are finished at once, flowing points
+// and loads a_n (in the first load step of a request without an initial
+// state it takes a_n = 0 instead, and points without flow write those
+// zeros, so the arena block needs no clearing at admission); points
+// without flow are finished at once, flowing points
 // are compacted into full waves (per-wave LDS queues, emptied before the
 // block moves to another request) and run the same per-point solve as the
 // plain evaluation kernel. Results therefore do not depend on what else is
