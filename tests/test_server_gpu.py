@@ -45,6 +45,9 @@ def _request(side, structure, seed, steps, phases=None, noise=2e-4, E=(5e-3, 0, 
 
 
 def _oracle_final(q, h=0.1, max_iter=50):
+    """The oracle's run of the request's load steps: final sigma and a, the
+    failed point solves, and the per-point strain scale max(||a||, ||eps||)
+    of the last step (see _check)."""
     n = q["phase"].size
     a = np.zeros((6, n)) if q.get("a_init") is None else np.array(q["a_init"], dtype=np.float64)
     fails = 0
@@ -53,12 +56,19 @@ def _oracle_final(q, h=0.1, max_iter=50):
         r = oracle.evaluate(eps, a, q["phase"], q["phases"], h=h, tol=1e-12, max_iter=max_iter)
         a = r["a_out"]
         fails += int((r["iters"] < 0).sum())
-    return r["sigma"], a, fails
+    return r["sigma"], a, fails, np.maximum(np.abs(a).max(0), np.abs(eps).max(0))
 
 
-def _check(res, sig_ref, a_ref):
+def _check(res, sig_ref, a_ref, scale):
+    """sigma within TOL per point; a (a strain) within TOL of the point's
+    strain scale max(||a||, ||eps||): both Newton solves stop at
+    ||F|| <= max(tol ||Delta||, 2^-48 ||eps - a_n||), so where the increment
+    of a point that starts from a_n = 0 is tiny (a flow just above the yield
+    stress) each side determines a only to about 2^-48 ||eps||, which is
+    far below TOL ||eps|| but can exceed TOL ||a||."""
     assert rel_per_point(res["sigma"], sig_ref).max() <= TOL
-    assert rel_per_point(res["a"], a_ref).max() <= TOL
+    r = np.abs(res["a"] - a_ref).max(0) / scale
+    assert r.max() <= TOL, (r.max(), int(r.argmax()))
 
 
 def test_single_request_matches_oracle():
@@ -68,9 +78,9 @@ def test_single_request_matches_oracle():
     (res,) = _drain(srv, [rid])
     srv.close()
     assert res["status"] == 0 and res["steps_done"] == 4 and res["n"] == 12 ** 3
-    sig, a, fails = _oracle_final(q)
+    sig, a, fails, scale = _oracle_final(q)
     assert res["nonconverged"] == fails == 0
-    _check(res, sig, a)
+    _check(res, sig, a, scale)
     assert np.abs(a).max() > 0
     assert res["t_arrival"] <= res["t_admit"] <= res["t_done"]
 
@@ -101,9 +111,9 @@ def test_batched_mix_matches_oracle_and_running_alone():
         # last bits, never more
         assert rel_per_point(m["sigma"], s["sigma"]).max() <= 1e-12
         assert rel_per_point(m["a"], s["a"]).max() <= 1e-12
-        sig, a, fails = _oracle_final(q)
+        sig, a, fails, scale = _oracle_final(q)
         assert m["nonconverged"] == fails
-        _check(m, sig, a)
+        _check(m, sig, a, scale)
 
 
 def test_point_cap_splits_batches():
@@ -115,8 +125,8 @@ def test_point_cap_splits_batches():
     srv.close()
     assert st["launches"] >= 4
     for q, r in zip(reqs, out):
-        sig, a, _ = _oracle_final(q)
-        _check(r, sig, a)
+        sig, a, _, scale = _oracle_final(q)
+        _check(r, sig, a, scale)
 
 
 def test_budget_admission_and_rejection():
@@ -156,9 +166,9 @@ def test_first_step_state_in_a_reused_block():
     finals = []
     for q, r in zip((first, second, third), out):
         assert r["status"] == 0
-        sig, a, fails = _oracle_final(q)
+        sig, a, fails, scale = _oracle_final(q)
         assert r["nonconverged"] == fails == 0
-        _check(r, sig, a)
+        _check(r, sig, a, scale)
         finals.append(a)
     kinds = np.array([p["kind"] for p in second["phases"]])
     leftover = (np.abs(finals[0]).max(axis=0) > 0) & (kinds[second["phase"]] == 0)
@@ -174,7 +184,7 @@ def test_nonconverged_points_are_counted():
     rid = srv.submit(**q, want_fields=True, max_iter=2)
     (res,) = _drain(srv, [rid])
     srv.close()
-    _, _, fails = _oracle_final(q, max_iter=2)
+    _, _, fails, _ = _oracle_final(q, max_iter=2)
     assert fails > 0 and res["nonconverged"] == fails
 
 
@@ -195,17 +205,17 @@ def test_invalid_requests():
 
 
 def test_mix_larger_than_the_resident_grid():
-    """More tiles in one batch than the batch kernel's resident grid holds
-    blocks (four 48^3 requests: 1728 tiles of 256 points against at most a
-    few blocks per compute unit), so blocks move from tile to tile and from
-    one request to the next inside a launch (drain the wave queues, reload
-    the descriptor and phase table): every request against the oracle and
-    against the same request served alone."""
+    """Many more tiles in one batch than the batch kernel's resident grid
+    holds blocks (four 84^3 requests: 9270 tiles of 256 points against at
+    most a few blocks per compute unit), so blocks stride over many tiles
+    and move from one request to the next inside a launch (drain the wave
+    queues, reload the descriptor and phase table): every request against
+    the oracle and against the same request served alone."""
     reqs = [_request(s, k, 60 + j, steps) for j, (s, k, steps) in
-            enumerate([(48, "fibre", 3), (48, "sphere", 2), (48, "fibre", 1), (48, "sphere", 4),
+            enumerate([(84, "fibre", 3), (84, "sphere", 2), (84, "fibre", 1), (84, "sphere", 4),
                        (11, "fibre", 2)])]
     tiles = sum((q["phase"].size + 255) // 256 for q in reqs)
-    assert tiles > 4 * torch.cuda.get_device_properties(0).multi_processor_count
+    assert tiles > 8 * 4 * torch.cuda.get_device_properties(0).multi_processor_count
     srv = _server()
     ids = [srv.submit(**q, want_fields=True) for q in reqs]
     mixed = _drain(srv, ids, timeout=120.0)
@@ -220,7 +230,7 @@ def test_mix_larger_than_the_resident_grid():
         assert m["status"] == s["status"] == 0
         assert rel_per_point(m["sigma"], s["sigma"]).max() <= 1e-12
         assert rel_per_point(m["a"], s["a"]).max() <= 1e-12
-        sig, a, fails = _oracle_final(q)
+        sig, a, fails, scale = _oracle_final(q)
         assert m["nonconverged"] == fails == 0
-        _check(m, sig, a)
+        _check(m, sig, a, scale)
         assert np.abs(a).max() > 0
