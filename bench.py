@@ -322,9 +322,9 @@ def main():
                          "1 GiB written) so profiler byte counters can be scaled")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported "
-                                   "(the per-point path shards by contiguous point ranges, "
-                                   "see the design notes)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus above 1 is not "
+                                   "supported (the per-point path would shard by contiguous "
+                                   "point ranges, one range per GPU)"}))
         sys.exit(2)
 
     # the serving stream's microstructures are generated in worker processes
