@@ -129,6 +129,10 @@ def load(path: str = LIB_PATH):
         raise RuntimeError(
             f"libautomat.so not found at {path}: build it with "
             "`python -m paper_2006_04391_amd.build` (there is no CPU fallback)")
+    # The library works on PyTorch's device memory and streams, so it must
+    # bind to the HIP runtime PyTorch loads; opened first, it would pull in
+    # another copy of the runtime, which PyTorch would then share.
+    import torch  # noqa: F401
     L = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         if not hasattr(L, name):
