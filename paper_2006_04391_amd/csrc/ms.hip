@@ -406,7 +406,10 @@ __global__ __launch_bounds__(kZ150Threads) void z150_gamma_kernel(hipfftDoubleCo
 // fields, plane-major spectra: plane (c, z) at spec + (6 z + c) 128 * 65).
 __global__ __launch_bounds__(slab::kThreads) void xy_forward_kernel(const double *tau,
                                                                     slab::cd *spec, int nz) {
-    __shared__ slab::cd L[slab::R * slab::LD];
+    // the packed plane (R x LD) and, at the end of each plane, its half
+    // spectrum in memory order (N x NH)
+    __shared__ slab::cd L[slab::N * slab::NH > slab::R * slab::LD ? slab::N * slab::NH
+                                                                   : slab::R * slab::LD];
     __shared__ slab::cd tw[slab::N];
     slab::init_twiddles(tw);
     __syncthreads();

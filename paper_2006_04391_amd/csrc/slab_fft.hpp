@@ -149,7 +149,10 @@ __device__ __forceinline__ void init_twiddles(cd *tw) {
 
 // One forward plane: v holds its rows (load_rows), dst receives the half
 // spectrum [128][65]; next (or null): the next plane, whose rows are loaded
-// into v once this plane's rows are in LDS. L: LDS plane, tw: twiddles.
+// into v once this plane's rows are in LDS. L: LDS of max(R LD, N NH)
+// complex values (the packed plane, then the half spectrum in memory order,
+// stored to dst in one contiguous pass so that every line is written whole);
+// tw: twiddles.
 // The rows of a real plane as the radix-16 pass takes them: lane l of packed
 // row g gets x = 8 n1 + l of rows 2g (real part) and 2g + 1 (imaginary part).
 __device__ __forceinline__ void load_rows(const double *__restrict__ src, cd *v) {
@@ -226,29 +229,32 @@ __device__ __forceinline__ void forward_plane(cd *v, const double *__restrict__ 
         }
         dft8<false>(a);
         dft8<false>(b);
-        if (g) {
+        __syncthreads();  // every column's cells are read
+        // stage the half spectrum in LDS in its memory order [ky][kx]; the
+        // packed column 0 goes to the kx = 0 slots for now
 #pragma unroll
-            for (int k2 = 0; k2 < 8; ++k2) {
-                dst[(l + 16 * k2) * NH + g] = a[k2];
-                dst[(l + 8 + 16 * k2) * NH + g] = b[k2];
-            }
-        }
-        __syncthreads();
-        if (g == 0) {
-#pragma unroll
-            for (int k2 = 0; k2 < 8; ++k2) {
-                L[cell(0, l + 16 * k2)] = a[k2];
-                L[cell(0, l + 8 + 16 * k2)] = b[k2];
-            }
+        for (int k2 = 0; k2 < 8; ++k2) {
+            L[(l + 16 * k2) * NH + g] = a[k2];
+            L[(l + 8 + 16 * k2) * NH + g] = b[k2];
         }
     }
     __syncthreads();
-    if (t < N) {
+    {
         // separate the spectra of the real columns kx = 0 and 64
-        const cd q = L[cell(0, t)], qm = L[cell(0, (N - t) & (N - 1))];
-        dst[t * NH] = {0.5 * (q.re + qm.re), 0.5 * (q.im - qm.im)};
-        dst[t * NH + R] = {0.5 * (q.im + qm.im), -0.5 * (q.re - qm.re)};
+        cd q{0.0, 0.0}, qm{0.0, 0.0};
+        if (t < N) {
+            q = L[t * NH];
+            qm = L[((N - t) & (N - 1)) * NH];
+        }
+        __syncthreads();
+        if (t < N) {
+            L[t * NH] = {0.5 * (q.re + qm.re), 0.5 * (q.im - qm.im)};
+            L[t * NH + R] = {0.5 * (q.im + qm.im), -0.5 * (q.re - qm.re)};
+        }
     }
+    __syncthreads();
+    // one contiguous store of the plane's half spectrum: whole lines
+    for (int k = t; k < N * NH; k += kThreads) dst[k] = L[k];
 }
 
 // One inverse plane: src half spectrum [128][65], then the strain update of
