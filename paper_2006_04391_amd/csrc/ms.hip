@@ -430,7 +430,10 @@ __global__ __launch_bounds__(slab::kThreads) void xy_forward_kernel(const double
 // of the change (partial[blockIdx.x], fixed order).
 __global__ __launch_bounds__(slab::kThreads) void xy_inverse_update_kernel(
     const slab::cd *spec, double *eps, int nz, double inv_n, double *partial) {
-    __shared__ slab::cd L[slab::R * slab::LD];
+    // the packed plane (R x LD) and, at the start of each plane, its half
+    // spectrum in memory order (N x NH)
+    __shared__ slab::cd L[slab::N * slab::NH > slab::R * slab::LD ? slab::N * slab::NH
+                                                                   : slab::R * slab::LD];
     __shared__ slab::cd tw[slab::N];
     __shared__ double red[slab::kThreads];
     slab::init_twiddles(tw);

@@ -21,6 +21,10 @@
 // update of the fixed-point iteration: eps' = raw / n, the tensor-norm
 // square of eps' - eps summed per work-group in a fixed order, eps <- eps'.
 //
+// The half spectrum moves between memory and LDS in one contiguous pass per
+// plane (its rows of 65 complex values start mid-line, so column-wise
+// accesses would touch each line more than once).
+//
 // LDS holds the packed plane as 64 rows of 128 complex values (pitch 129).
 // After the row pass, column j (0 .. 63) keeps its 128 values in the cells
 // (q, j) and (q, 128 - j) of rows q = 0 .. 63 (column 0: (q, 0) and (q, 64)),
@@ -259,7 +263,10 @@ __device__ __forceinline__ void forward_plane(cd *v, const double *__restrict__ 
 
 // One inverse plane: src half spectrum [128][65], then the strain update of
 // the real plane eps [128][128] with raw = the unnormalised inverse:
-// eps' = raw * inv_n, acc += wgt * (eps' - eps)^2, eps <- eps'.
+// eps' = raw * inv_n, acc += wgt * (eps' - eps)^2, eps <- eps'. L: LDS of
+// max(R LD, N NH) complex values (the half spectrum in memory order, loaded
+// in one contiguous pass so that every line is read whole, then the packed
+// plane).
 __device__ __forceinline__ void inverse_plane_update(const cd *__restrict__ src,
                                                      double *__restrict__ eps, double inv_n,
                                                      double wgt, double &acc, cd *L,
@@ -267,15 +274,20 @@ __device__ __forceinline__ void inverse_plane_update(const cd *__restrict__ src,
     const int t = threadIdx.x;
     const int g = t >> 3, l = t & 7;
     {
-        // columns (column 0 packs kx = 0 and 64): radix-16 pass from memory
+        // the half spectrum into LDS in memory order (one contiguous load:
+        // whole lines), then the columns (column 0 packs kx = 0 and 64):
+        // radix-16 pass
+        __syncthreads();  // the previous plane's last reads of L are done
+        for (int k = t; k < N * NH; k += kThreads) L[k] = src[k];
+        __syncthreads();
         cd v[16];
 #pragma unroll
         for (int n1 = 0; n1 < 16; ++n1) {
             const int ky = 8 * n1 + l;
             if (g) {
-                v[n1] = src[ky * NH + g];
+                v[n1] = L[ky * NH + g];
             } else {
-                const cd s0 = src[ky * NH], s64 = src[ky * NH + R];
+                const cd s0 = L[ky * NH], s64 = L[ky * NH + R];
                 v[n1] = {s0.re - s64.im, s0.im + s64.re};
             }
         }
