@@ -30,6 +30,15 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 BYTES_PER_POINT = 6 * 8 + 6 * 8 + 1 + 6 * 8 + 6 * 8          # 193
 BYTES_PER_POINT_TANGENT = BYTES_PER_POINT + 36 * 8            # 481
+# the conventional entry point also writes its per-point iteration count
+BYTES_PER_POINT_CONVENTIONAL = BYTES_PER_POINT + 4             # 197
+# FP32: float fields, 36 float tangent components
+BYTES_PER_POINT_F32 = 4 * 24 + 1                               # 97
+BYTES_PER_POINT_F32_TANGENT = BYTES_PER_POINT_F32 + 36 * 4     # 241
+# adaptive schemes: eps_n, eps_{n+1}, a_n and the phase in; sigma, a_{n+1}
+# and the accepted step count out
+BYTES_PER_POINT_RK = 3 * 6 * 8 + 1 + 2 * 6 * 8 + 4             # 245
+BYTES_PER_POINT_RK_TANGENT = BYTES_PER_POINT_RK + 36 * 8       # 533
 
 
 # HBM bytes per launch of the forward kernel measured with rocprofv3
@@ -71,6 +80,14 @@ def kernel_source_hash():
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def hbm_roofline(bytes_per_point, n, ms):
+    """HBM roofline of a leg: its algorithmic bytes per point times the
+    points of one launch over the measured time per launch."""
+    gbs = bytes_per_point * n / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "bytes_per_point": bytes_per_point, "achieved": gbs,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
 
 
 def time_calls(fn, steps, warmup, stream):
@@ -425,7 +442,8 @@ def main():
     a51 = BYTES_PER_POINT * n / (ms51 * 1e-3) / 1e9
     out["exponent_5_1"] = {"workload": "same 256^3 batch, matrix exponent n = 5.1",
                            "ms_per_step": ms51, "value": n / (ms51 * 1e-3), "unit": "updates/s",
-                           "roofline_frac": a51 / HBM_PEAK_GBS}
+                           "roofline_frac": a51 / HBM_PEAK_GBS,
+                           "roofline": hbm_roofline(BYTES_PER_POINT, n, ms51)}
     log(f"[bench] n = 5.1: {ms51:.3f} ms/step, {a51 / HBM_PEAK_GBS:.3f} of the HBM roofline")
 
     out["latency_4096"] = latency_c0(dev)
@@ -441,7 +459,8 @@ def main():
         tt, each_t, _ = time_calls(step_t, max(5, args.steps // 2), 2, stream)
         ms_t = tt / max(5, args.steps // 2)
         out["tangent"] = {"ms_per_step": ms_t, "value": n / (ms_t * 1e-3), "unit": "updates/s",
-                          "hbm_gbs": BYTES_PER_POINT_TANGENT * n / (ms_t * 1e-3) / 1e9}
+                          "hbm_gbs": BYTES_PER_POINT_TANGENT * n / (ms_t * 1e-3) / 1e9,
+                          "roofline": hbm_roofline(BYTES_PER_POINT_TANGENT, n, ms_t)}
         log(f"[bench] tangent: {ms_t:.3f} ms/step")
 
     # the paper's conventional strategy (hand-reduced radial return, no AD)
@@ -453,7 +472,8 @@ def main():
     ms_cv = tc / max(3, args.steps // 2)
     out["conventional"] = {"workload": "same 256^3 batch, radial return (scalar Newton, no AD)",
                            "ms_per_step": ms_cv, "value": n / (ms_cv * 1e-3), "unit": "updates/s",
-                           "automatic_over_conventional_time": ms / ms_cv}
+                           "automatic_over_conventional_time": ms / ms_cv,
+                           "roofline": hbm_roofline(BYTES_PER_POINT_CONVENTIONAL, n, ms_cv)}
     log(f"[bench] conventional: {ms_cv:.3f} ms/step (automatic / conventional = {ms / ms_cv:.2f})")
     if not args.no_tangent:
         def step_cvt():
@@ -463,6 +483,8 @@ def main():
         tct, _, _ = time_calls(step_cvt, max(5, args.steps // 2), 2, stream)
         cv_t = tct / max(5, args.steps // 2)
         out["conventional"]["tangent_ms_per_step"] = cv_t
+        out["conventional"]["tangent_roofline"] = hbm_roofline(
+            BYTES_PER_POINT_CONVENTIONAL + 36 * 8, n, cv_t)
         if "tangent" in out:
             out["conventional"]["automatic_over_conventional_time_tangent"] = (
                 out["tangent"]["ms_per_step"] / cv_t)
@@ -479,7 +501,8 @@ def main():
     ms_sa = ts / max(3, args.steps // 2)
     sa = {"workload": "same 256^3 batch, hand-derived partials in the generic Newton solve",
           "ms_per_step": ms_sa, "value": n / (ms_sa * 1e-3), "unit": "updates/s",
-          "automatic_over_semi_automatic_time": ms / ms_sa}
+          "automatic_over_semi_automatic_time": ms / ms_sa,
+          "roofline": hbm_roofline(BYTES_PER_POINT, n, ms_sa)}
     if not args.no_tangent:
         def step_sat():
             api.evaluate(eps, a_old, phase, ps.phases, ps.h, ps.tol, ps.max_iter,
@@ -487,6 +510,8 @@ def main():
                          tangent_out=tan_out)
         tst, _, _ = time_calls(step_sat, max(5, args.steps // 2), 2, stream)
         sa["tangent_ms_per_step"] = tst / max(5, args.steps // 2)
+        sa["tangent_roofline"] = hbm_roofline(BYTES_PER_POINT_TANGENT, n,
+                                              sa["tangent_ms_per_step"])
         if "tangent" in out:
             sa["automatic_over_semi_automatic_time_tangent"] = (out["tangent"]["ms_per_step"] /
                                                                 sa["tangent_ms_per_step"])
@@ -510,8 +535,10 @@ def main():
     f32 = {"workload": "same 256^3 batch rounded to float32, FP32 arithmetic, tol 1e-6 (floor "
                        "at the FP32 rounding level)",
            "ms_per_step": ms_32, "value": n / (ms_32 * 1e-3), "unit": "updates/s",
-           "bytes_per_point": 4 * 24 + 1, "hbm_gbs": (4 * 24 + 1) * n / (ms_32 * 1e-3) / 1e9,
-           "fp64_over_fp32_time": ms / ms_32}
+           "bytes_per_point": BYTES_PER_POINT_F32,
+           "hbm_gbs": BYTES_PER_POINT_F32 * n / (ms_32 * 1e-3) / 1e9,
+           "fp64_over_fp32_time": ms / ms_32,
+           "roofline": hbm_roofline(BYTES_PER_POINT_F32, n, ms_32)}
     if not args.no_tangent:
         tan32 = torch.empty((36, n), dtype=torch.float32, device=dev)
 
@@ -520,6 +547,8 @@ def main():
                              sigma_out=sig32, a_out=an32, tangent=True, tangent_out=tan32)
         t32t, _, _ = time_calls(step_32t, max(5, args.steps // 2), 2, stream)
         f32["tangent_ms_per_step"] = t32t / max(5, args.steps // 2)
+        f32["tangent_roofline"] = hbm_roofline(BYTES_PER_POINT_F32_TANGENT, n,
+                                               f32["tangent_ms_per_step"])
         del tan32
         if "tangent" in out:
             f32["fp64_over_fp32_time_tangent"] = (out["tangent"]["ms_per_step"] /
@@ -551,7 +580,8 @@ def main():
                                      "h = 0.1 s, atol 1e-6, rtol 1e-3 (no tangent)",
                          "ms_per_step": ms_rk, "value": n / (ms_rk * 1e-3), "unit": "updates/s",
                          "accepted_steps_histogram": {int(k): int(v) for k, v in
-                                                      zip(*np.unique(st, return_counts=True))}}
+                                                      zip(*np.unique(st, return_counts=True))},
+                         "roofline": hbm_roofline(BYTES_PER_POINT_RK, n, ms_rk)}
             log(f"[bench] {pair}: {ms_rk:.3f} ms/step")
             # with the consistent tangent (the sensitivity system integrated
             # alongside and inside the error measure)
@@ -566,6 +596,9 @@ def main():
             ms_rk_t = tt_rk / 3
             st_t = steps_rk["tan"].cpu().numpy()
             out[pair]["tangent_ms_per_step"] = ms_rk_t
+            # bound by the FP64 work of its stage Hessians and sensitivity
+            # columns, not by memory: the HBM fraction shows how far
+            out[pair]["tangent_roofline"] = hbm_roofline(BYTES_PER_POINT_RK_TANGENT, n, ms_rk_t)
             out[pair]["tangent_accepted_steps_histogram"] = {
                 int(k): int(v) for k, v in zip(*np.unique(st_t, return_counts=True))}
             log(f"[bench] {pair} with tangent: {ms_rk_t:.3f} ms/step")
