@@ -643,6 +643,17 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = {"read": src.numel() * 8, "write": dst.numel() * 8}
+        # the rate of a plain device copy: what the memory system gives a
+        # kernel that only streams (read + write bytes over the time)
+        c0 = torch.cuda.Event(enable_timing=True)
+        c1 = torch.cuda.Event(enable_timing=True)
+        c0.record()
+        for _ in range(10):
+            dst.copy_(src)
+        c1.record()
+        torch.cuda.synchronize()
+        out["copy_gbs"] = 2 * src.numel() * 8 * 10 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+        log(f"[bench] 1 GiB device copy: {out['copy_gbs']:.0f} GB/s (read + write)")
 
     print(json.dumps(out), flush=True)
 
